@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput of the sparse, truncated state-vector hot path on one MI355X.
+
+A step is one gate step of the whole hot path: group the state by the bits
+outside the gate, apply the gate with the collision merge, rank, cut (p-mass
+then top-k), renormalise and write the survivors. The default workload is the
+48-qubit peaked circuit (16 + 16 layers of 24 Haar SU(4) on random qubit
+pairs, eps = 0.01, complex64 amplitudes), cut to min(K = 2^24, L_0.99) after
+every SU(4) step. Warm-up steps bring the state to its steady size (2^24
+terms); the timed steps then continue the same circuit.
+
+metric: gate-term updates/s = (input terms of the timed steps) / time.
+roofline: the kernel kind with the largest share of the step time, its
+algorithmic bytes per launch over its average launch time (HIP events on the
+library's stream), against 8 TB/s.
+cpu_baseline: the C oracle (one thread) on one gate step of a bounded sample
+of the steady-state GPU state.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per unit for each kernel kind (c64: 8-byte key + 8-byte
+# amplitude per term; c128: 8 + 16). Units: input terms of the launch, plus
+# output terms where a kernel writes them.
+def kernel_bytes(kind: str, amp_bytes: int, n_in: float, n_out: float, n_side: float) -> float:
+    term = 8 + amp_bytes
+    if kind == "radix_pass":
+        return 2 * term * n_in          # read and write every term once
+    if kind == "radix_hist":
+        return 8 * n_in                 # keys only
+    if kind == "group_hist":
+        return term * n_in              # read every term once (partners are neighbours)
+    if kind == "group_extract":
+        return term * n_in + 16 * n_side
+    if kind == "group_emit":
+        return term * n_in + term * n_out
+    if kind == "side_hist":
+        return 8 * n_side
+    return 0.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300, help="timed gate steps")
+    ap.add_argument("--warmup", type=int, default=30, help="untimed gate steps before timing")
+    ap.add_argument("--profile-steps", type=int, default=60, help="gate steps timed per kernel")
+    ap.add_argument("--workload", default="48q", choices=["48q", "24q"])
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="terms in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
+              "(sharding by global key bits), not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2607_07816_amd import circuits as C
+    from paper_2607_07816_amd._lib import State
+
+    if args.workload == "48q":
+        circuit, cfg = C.workload_48q()
+        prec = cfg["precision"]
+    else:
+        circuit, cfg = C.workload_24q()
+        prec = "c64"
+    K, p = cfg["K"], cfg["p"]
+    amp_bytes = 8 if prec == "c64" else 16
+    steps_avail = [i for i, t in enumerate(circuit.truncate_after) if t]
+    need = args.warmup + args.steps + args.profile_steps + 1
+    if need > len(steps_avail):
+        raise SystemExit(f"the circuit has {len(steps_avail)} truncated steps; asked for {need}")
+
+    torch.cuda.init()
+    dev = torch.cuda.current_device()
+    log(f"device {torch.cuda.get_device_name(dev)}; workload {circuit.name} n={circuit.n} K={K} p={p} {prec}")
+    st = State(circuit.n, K=K, p=p, precision=prec, capacity=K)
+    gi = 0
+
+    def run(nsteps):
+        nonlocal gi
+        done = 0
+        while done < nsteps:
+            qs, U = circuit.gates[gi]
+            st.apply_gate(qs, U)
+            if circuit.truncate_after[gi]:
+                st.truncate()
+                done += 1
+            gi += 1
+
+    t_w = time.perf_counter()
+    run(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warm-up {args.warmup} steps in {time.perf_counter() - t_w:.2f}s; terms {st.num_terms()}")
+
+    # timed region
+    c0 = st.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = st.counters()
+    updates = c1["term_updates"] - c0["term_updates"]
+    elapsed = t1 - t0
+    value = updates / elapsed
+    log(f"timed {args.steps} steps: {elapsed:.3f}s, {updates} updates, {value:.3e} updates/s")
+
+    # per-kernel timing over further steps (HIP events on the library's stream)
+    st.profile(True)
+    st.kernel_times(reset=True)
+    c2 = st.counters()
+    run(args.profile_steps)
+    kt = st.kernel_times()
+    c3 = st.counters()
+    st.profile(False)
+    nsteps = c3["gate_steps"] - c2["gate_steps"]
+    n_in = (c3["term_updates"] - c2["term_updates"]) / max(nsteps, 1)
+    n_cand = (c3["candidates"] - c2["candidates"]) / max(nsteps, 1)
+    n_out = min(n_in, K)
+    n_side = n_cand / 8.0  # not measured per launch; only matters if side_hist dominates
+    total_ms = sum(v[0] for v in kt.values())
+    dom = max(kt, key=lambda k: kt[k][0])
+    dom_ms, dom_n = kt[dom]
+    avg_s = dom_ms / max(dom_n, 1) / 1e3
+    per_launch = kernel_bytes(dom, amp_bytes, n_in, n_out, n_side)
+    achieved = per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    step_bytes = sum(kernel_bytes(k, amp_bytes, n_in, n_out, n_side) * (v[1] / max(nsteps, 1))
+                     for k, v in kt.items())
+    log("kernel shares: " + ", ".join(f"{k} {v[0] / max(total_ms, 1e-9) * 100:.1f}% ({v[1]})"
+                                      for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])))
+    log(f"dominant {dom}: {avg_s * 1e6:.1f} us/launch, {per_launch / 1e6:.1f} MB/launch, {achieved:.0f} GB/s")
+
+    key, prob = st.peak()
+    log(f"state peak {key:#x} prob {prob:.4f} (hidden {circuit.hidden:#x})")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(st, circuit, gi, K, p, args.cpu_sample)
+    st.close()
+
+    line = {
+        "metric": "gate-term updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {
+            "workload": circuit.name + f"_K2^{K.bit_length() - 1}_p{p}_{prec}",
+            "n_qubits": circuit.n,
+            "K": K,
+            "p": p,
+            "terms_per_step": n_in,
+            "candidates_per_step": n_cand,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "step_algorithmic_GBps": step_bytes / (total_ms / max(nsteps, 1) / 1e3) / 1e9 if total_ms else None,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(st, circuit, gi, K, p, sample_terms):
+    """Time the C oracle on one gate step of a sample of the GPU's state."""
+    import numpy as np
+
+    from oracle import c_oracle
+
+    keys, amps = st.read_terms()
+    n = keys.shape[0]
+    take = min(sample_terms, n)
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(n, size=take, replace=False)) if take < n else np.arange(n)
+    k, a = keys[idx], amps[idx]
+    kk = max(1, int(K * take / max(n, 1)))
+    # next truncated gate of the circuit
+    while not circuit.truncate_after[gi]:
+        gi += 1
+    qs, U = circuit.gates[gi]
+    c_oracle.build()
+    t0 = time.perf_counter()
+    k2, a2, info = c_oracle.step(k, a, qs, U, kk, p, True)
+    dt = time.perf_counter() - t0
+    log(f"cpu oracle: {take} terms, K={kk}: {dt:.2f}s")
+    return {
+        "value": take / dt,
+        "unit": "updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one gate step (apply + truncate) of the plain C oracle on {take} of the {n} steady-state "
+                  f"terms (random subset), K scaled to {kk}, p={p}, FP64",
+    }
+
+
+if __name__ == "__main__":
+    main()

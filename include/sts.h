@@ -1,0 +1,176 @@
+/*
+ * sts.h - C ABI of the sparse, truncated state-vector library (gfx950).
+ *
+ * The library keeps a quantum state as a sparse list of (basis key, complex
+ * amplitude) terms in device memory and offers the operations the paper
+ * builds its simulator from:
+ *
+ *   sts_init        - a state of n <= 64 qubits in the ground state |0...0>,
+ *                     stored as a single term (Sec. I); basis keys are 64-bit
+ *                     integers, so n is at most 64 (Sec. V).
+ *   sts_apply_gate  - apply a 2^m x 2^m unitary to m qubits: each amplitude
+ *                     multiplies the column of U picked by its bit pattern on
+ *                     those qubits, the new keys follow from bit operations,
+ *                     and contributions to the same key are summed (Eq. (3)
+ *                     and its m-qubit generalisation, Sec. IV.A).
+ *   sts_truncate    - keep the largest-|a|^2 terms: p-mass first, then top-k,
+ *                     then renormalise (Sec. III; Sec. IV.B).
+ *   sts_peak        - the most probable basis key (Sec. I); only this result
+ *                     crosses to the host (Sec. V).
+ *
+ * Conventions
+ *   - Qubit q is bit q of a key (qubit 0 = least significant bit).
+ *   - U is row-major, 2^m x 2^m, complex, FP64, interleaved (re, im):
+ *     U[2*(i*2^m + j) + 0/1]. U[i][j] maps local pattern j to local pattern i,
+ *     where bit t of a local pattern is qubit qubits[t]. U is not checked for
+ *     unitarity.
+ *   - Amplitudes are complex128 (STS_C128) or complex64 (STS_C64). With
+ *     STS_C64 the gate arithmetic and stored amplitudes are FP32 (U is
+ *     rounded to FP32, nearest-even, once per call), while |a|^2, the
+ *     truncation threshold, the probability-mass sums and the
+ *     renormalisation scale stay FP64.
+ *   - Ranking is the total order (|a|^2 descending, key ascending), with
+ *     |a|^2 = fl64(fl64(re*re) + fl64(im*im)) (components promoted to FP64
+ *     first). A term is dropped by gate application only when both parts
+ *     are exactly zero.
+ *   - Truncation keeps L = min(L_p, K, C) terms of the C present, where L_p
+ *     is the shortest prefix of the ranked terms whose exact mass is
+ *     >= p * W (W = exact current total). K = 0 turns top-k off; p <= 0 or
+ *     p >= 1 turns p-mass off. If L = C nothing changes (no rescale);
+ *     otherwise every kept amplitude is multiplied by fl64(1/sqrt(S)), with
+ *     S the correctly rounded kept mass.
+ *
+ * Execution, ownership, errors
+ *   - All calls are ordered on the stream given to sts_init and return
+ *     without waiting for the GPU, except those marked "synchronises".
+ *     The term count stays on the device between calls.
+ *   - Host arrays passed in are read before the call returns; the caller
+ *     keeps ownership. Device memory is owned by the context: either carved
+ *     from the caller's arena (which must stay allocated until sts_free) or
+ *     allocated by the library.
+ *   - A context is not thread-safe; distinct contexts may run concurrently
+ *     on distinct streams.
+ *   - STS_E_ARG and STS_E_CAPACITY leave the state as it was. STS_E_HIP
+ *     and STS_E_NOMEM during a computation poison the context: afterwards
+ *     only sts_free is valid (other calls return STS_E_STATE).
+ */
+#ifndef STS_H
+#define STS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STS_OK = 0,
+    STS_E_ARG = -1,      /* invalid argument; nothing changed                  */
+    STS_E_NOMEM = -2,    /* device allocation failed                           */
+    STS_E_CAPACITY = -3, /* the result would not fit in the context's capacity  */
+    STS_E_HIP = -4,      /* a HIP runtime call failed                          */
+    STS_E_STATE = -5     /* the context is poisoned or the call is out of order */
+} sts_status;
+
+typedef enum { STS_C128 = 0, STS_C64 = 1 } sts_precision;
+
+typedef struct sts_ctx sts_ctx;
+
+/*
+ * Device bytes a context needs to hold up to cap_terms terms at the given
+ * precision (for sizing an arena). Writes the size to *bytes.
+ */
+sts_status sts_required_bytes(uint64_t cap_terms, int precision, size_t *bytes);
+
+/*
+ * Create a state of n_qubits (1..64) in the ground state (one term, key 0,
+ * amplitude 1). max_terms = K of top-k truncation (0 = off); mass = p of
+ * p-mass truncation (off unless 0 < p < 1). Both may be given: p-mass first,
+ * then top-k (Sec. III). hip_stream: a hipStream_t, NULL = the null stream.
+ * arena/arena_bytes: device memory to carve every buffer from (NULL/0 = the
+ * library allocates). cap_terms: the most terms the state may ever hold;
+ * 0 = max(K, 2^20) when the library allocates, or as many as the arena holds.
+ * Gate application needs room for the 2^m * N candidates only when the state
+ * is not truncated right after (see sts_apply_gate).
+ */
+sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass,
+                    int precision, void *hip_stream, void *arena, size_t arena_bytes,
+                    uint64_t cap_terms);
+
+/*
+ * Apply the gate U (host array, 2*4^m doubles, layout above) on the m
+ * distinct qubits qubits[0..m-1] (each < n), 1 <= m <= 5. The result is
+ * formed lazily: the grouping work runs now, and the new amplitudes are
+ * produced by the following sts_truncate (so candidates are never stored),
+ * or by the next call that needs them. Returns STS_E_ARG for bad arguments
+ * and STS_E_CAPACITY if the un-truncated result of the previous gate does
+ * not fit (then that previous gate is dropped and the state is the one
+ * before it).
+ */
+sts_status sts_apply_gate(sts_ctx *ctx, int m, const int *qubits, const double *U);
+
+/* Truncate by the rule fixed at sts_init (see above) and renormalise. */
+sts_status sts_truncate(sts_ctx *ctx);
+
+/* Most probable key (ties to the smaller key) and its probability
+ * |a|^2 / W, W the exact current total. Synchronises. */
+sts_status sts_peak(sts_ctx *ctx, uint64_t *key, double *prob);
+
+/* Number of terms now held. Synchronises. */
+sts_status sts_num_terms(sts_ctx *ctx, uint64_t *n);
+
+/* Copy the terms to the host in ascending key order, amplitudes as FP64
+ * (re, im) pairs; keys[cap], amps[2*cap]. *n receives the count; returns
+ * STS_E_CAPACITY (copying nothing) if cap is too small. Synchronises. */
+sts_status sts_read_terms(sts_ctx *ctx, uint64_t cap, uint64_t *keys, double *amps, uint64_t *n);
+
+/* Replace the state with n terms from the host (keys unique and < 2^n_qubits,
+ * amplitudes FP64 (re, im); rounded to FP32 for STS_C64). */
+sts_status sts_load_terms(sts_ctx *ctx, uint64_t n, const uint64_t *keys, const double *amps);
+
+/* Figures of the last sts_truncate: W = total mass before the cut (correctly
+ * rounded), kept_fraction = S/W, log10_cum_kept = sum of log10 of every kept
+ * fraction so far, last_candidates = number of nonzero terms before the cut.
+ * Any pointer may be NULL. Synchronises. */
+sts_status sts_stats(sts_ctx *ctx, double *W, double *kept_fraction, double *log10_cum_kept,
+                     uint64_t *last_candidates);
+
+/* Cumulative counters since sts_init: truncations run (gate steps), input
+ * terms they processed (gate-term updates) and candidates they ranked. Any
+ * pointer may be NULL. Synchronises. */
+sts_status sts_counters(sts_ctx *ctx, uint64_t *gate_steps, uint64_t *term_updates, uint64_t *candidates);
+
+/* Kernel kinds timed by sts_profile (the kernels of a gate step). */
+typedef enum {
+    STS_K_RADIX_HIST = 0,   /* digit histogram of the grouping sort          */
+    STS_K_RADIX_SCAN = 1,   /* digit offsets                                 */
+    STS_K_RADIX_PASS = 2,   /* one scatter pass of the grouping sort         */
+    STS_K_GROUP_HIST = 3,   /* gate + weight histogram pass                  */
+    STS_K_PICK1 = 4,        /* exponent-level cut                            */
+    STS_K_GROUP_EXTRACT = 5,/* gate + copy of the cut's exponent             */
+    STS_K_SIDE_HIST = 6,    /* mantissa-level cut                            */
+    STS_K_FINAL = 7,        /* last levels and LDS sort                      */
+    STS_K_GROUP_EMIT = 8,   /* gate + survivor write                         */
+    STS_K_COUNT = 9
+} sts_kernel_kind;
+
+/* Turn per-kernel timing on (1) or off (0). While on, every kernel launch is
+ * bracketed by HIP events on the context's stream. */
+sts_status sts_profile(sts_ctx *ctx, int enable);
+
+/* Total time (ms) and number of launches of one kernel kind since timing was
+ * turned on (or last reset with reset = 1). Synchronises. */
+sts_status sts_kernel_time(sts_ctx *ctx, int kind, int reset, double *total_ms, uint64_t *launches);
+
+/* Release the context and the device memory it allocated. NULL is a no-op. */
+void sts_free(sts_ctx *ctx);
+
+/* Static description of a status code. */
+const char *sts_strerror(sts_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STS_H */

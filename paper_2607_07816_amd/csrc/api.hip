@@ -1,0 +1,702 @@
+// api.hip - the C ABI of libsts: context, device memory, and the order in
+// which the kernels of a gate step run.
+//
+// A gate step (sts_apply_gate then sts_truncate) runs, on the context's
+// stream and without host synchronisation:
+//   1. radix histogram + scan + 1..4 scatter passes: group the state by the
+//      hash bucket of the bits outside the gate (radix.hip);
+//   2. histogram pass: recompute every new amplitude, histogram its weight by
+//      exponent field with exact mantissa sums (group.hip);
+//   3. level-1 pick: exact prefix over exponent bins (select.hip);
+//   4. extraction pass: copy the candidates of the cut's exponent to the side
+//      buffer (group.hip);
+//   5. level-2 histogram + pick over the side buffer, then the final levels
+//      and an LDS sort of the last <= 4096 candidates (select.hip);
+//   6. write pass: recompute once more and write the survivors, rescaled
+//      (group.hip).
+// Without a truncation rule (or when the next gate arrives first) step 6
+// alone runs, keeping every nonzero candidate.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sts.h"
+#include "kernels.h"
+
+namespace {
+
+constexpr u64 kAlign = 256;
+constexpr int kULen = 32 * 32 * 2; // doubles of the largest U
+
+u64 align_up(u64 x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
+
+struct Layout {
+    u64 ctl, keys[3], amps[3], side_key, side_w, h1, h2, best, rhist, roffs, look_radix, look_comp, tctr, dU, total;
+};
+
+Layout make_layout(u64 cap, int prec)
+{
+    const u64 asz = prec == STS_C128 ? 16 : 8;
+    const u64 scap = 4 * cap;
+    const u64 tiles = ceil_div(cap, STS_TILE);
+    const u64 gtiles = ceil_div(cap, STS_GTILE);
+    Layout L;
+    u64 o = 0;
+    auto take = [&](u64 bytes) {
+        const u64 at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.ctl = take(sizeof(DevCtl));
+    for (int i = 0; i < 3; ++i) L.keys[i] = take(cap * 8);
+    for (int i = 0; i < 3; ++i) L.amps[i] = take(cap * asz);
+    L.side_key = take(scap * 8);
+    L.side_w = take(scap * 8);
+    L.h1 = take(3 * STS_NBIN * 8);
+    L.h2 = take(3 * STS_NBIN * 8);
+    L.best = take(2 * STS_MAX_GROUPS * 8);
+    L.rhist = take(STS_MAX_PASSES * 256 * 8);
+    L.roffs = take(STS_MAX_PASSES * 256 * 8);
+    L.look_radix = take(STS_MAX_PASSES * tiles * 256 * 8);
+    L.look_comp = take(gtiles * 8);
+    L.tctr = take(16 * 4);
+    L.dU = take(kULen * 8);
+    L.total = o;
+    return L;
+}
+
+} // namespace
+
+struct sts_ctx {
+    int n_qubits = 0;
+    int prec = 0;
+    u64 K = 0;
+    double p = 0.0;
+    hipStream_t stream = nullptr;
+    bool own_mem = false;
+    unsigned char *mem = nullptr;
+    u64 cap = 0, scap = 0, tiles_cap = 0, gtiles_cap = 0;
+    u64 *keys[3] = {nullptr, nullptr, nullptr};
+    void *amps[3] = {nullptr, nullptr, nullptr};
+    int cur = 0;            // buffer with the state, or the sorted input of the pending gate
+    bool pending = false;   // a gate whose new amplitudes are not written yet
+    GateArg gate;
+    u64 n_bound = 1;        // upper bound on the terms in buffer cur
+    DevCtl *ctl = nullptr;
+    u64 *h1 = nullptr, *h2 = nullptr, *best = nullptr;
+    u64 *side_key = nullptr, *side_w = nullptr;
+    u64 *rhist = nullptr, *roffs = nullptr, *look_radix = nullptr, *look_comp = nullptr;
+    u32 *tctr = nullptr;
+    double *dU = nullptr;
+    double *hU = nullptr;    // pinned staging of U for m >= 4
+    hipEvent_t u_event = nullptr;
+    bool u_event_live = false;
+    DevCtl *hctl = nullptr;  // pinned mirror of the control block
+    u32 epoch = 0;
+    bool poisoned = false;
+    // optional per-kernel timing
+    bool prof = false;
+    struct Mark {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[STS_K_COUNT] = {};
+    u64 prof_n[STS_K_COUNT] = {};
+};
+
+namespace {
+
+sts_status fail_hip(sts_ctx *c, hipError_t e)
+{
+    if (e == hipSuccess) return STS_OK;
+    if (c) c->poisoned = true;
+    return e == hipErrorOutOfMemory ? STS_E_NOMEM : STS_E_HIP;
+}
+
+#define STS_TRY(c, expr)                                   \
+    do {                                                   \
+        const hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return fail_hip((c), _e);    \
+    } while (0)
+
+hipEvent_t prof_event(sts_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// a kernel launch, bracketed by events when timing is on
+#define STS_LAUNCH(c, kind, expr)                                                  \
+    do {                                                                           \
+        hipEvent_t _a = nullptr, _b = nullptr;                                     \
+        if ((c)->prof) {                                                           \
+            _a = prof_event(c);                                                    \
+            _b = prof_event(c);                                                    \
+            if (_a && _b) STS_TRY(c, hipEventRecord(_a, (c)->stream));             \
+        }                                                                          \
+        STS_TRY(c, expr);                                                          \
+        if (_a && _b) {                                                            \
+            STS_TRY(c, hipEventRecord(_b, (c)->stream));                           \
+            (c)->marks.push_back({(kind), _a, _b});                                \
+        }                                                                          \
+    } while (0)
+
+// fold finished marks into the per-kind totals (after a synchronisation)
+void prof_collect(sts_ctx *c)
+{
+    for (auto &m : c->marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+            c->prof_ms[m.kind] += ms;
+            c->prof_n[m.kind] += 1;
+        }
+        c->pool.push_back(m.a);
+        c->pool.push_back(m.b);
+    }
+    c->marks.clear();
+}
+
+u32 next_epoch(sts_ctx *c)
+{
+    if (++c->epoch >= (1u << 24)) {
+        // tags wrap: clear every look-back word once
+        (void)hipMemsetAsync(c->look_radix, 0, STS_MAX_PASSES * c->tiles_cap * 256 * 8, c->stream);
+        (void)hipMemsetAsync(c->look_comp, 0, c->gtiles_cap * 8, c->stream);
+        c->epoch = 1;
+    }
+    return c->epoch;
+}
+
+u64 sat_shl(u64 x, int m)
+{
+    if (m <= 0) return x;
+    if (x > (~0ull >> m)) return ~0ull;
+    return x << m;
+}
+
+PassBufs pass_bufs(sts_ctx *c, int in, int out)
+{
+    PassBufs b;
+    std::memset(&b, 0, sizeof(b));
+    b.keys = c->keys[in];
+    b.amps = c->amps[in];
+    b.n_in = &c->ctl->cnt[in];
+    b.n_out = out >= 0 ? &c->ctl->cnt[out] : nullptr;
+    b.ctl = c->ctl;
+    b.h1 = c->h1;
+    b.best = c->best;
+    b.side_key = c->side_key;
+    b.side_w = c->side_w;
+    b.side_cap = c->scap;
+    if (out >= 0) {
+        b.out_keys = c->keys[out];
+        b.out_amps = c->amps[out];
+    }
+    b.out_cap = c->cap;
+    b.look = c->look_comp;
+    b.tile_ctr = c->tctr + 4;
+    return b;
+}
+
+int hist_groups(u64 n_bound)
+{
+    const u64 g = ceil_div(n_bound ? n_bound : 1, STS_WG);
+    return (int)std::min<u64>(std::max<u64>(g, 1), STS_MAX_GROUPS);
+}
+
+int compact_tiles(u64 n_bound) { return (int)std::max<u64>(ceil_div(n_bound, STS_GTILE), 1); }
+
+// copy the control block to the host and wait; map device-side error flags
+sts_status sync_ctl(sts_ctx *c)
+{
+    STS_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, c->stream));
+    STS_TRY(c, hipStreamSynchronize(c->stream));
+    const u32 f = c->hctl->flags;
+    if (f & (STS_F_SIDE_OVERFLOW | STS_F_OUT_OVERFLOW)) {
+        c->poisoned = true;
+        return STS_E_CAPACITY;
+    }
+    if (f & STS_F_UNRESOLVED) {
+        c->poisoned = true;
+        return STS_E_STATE;
+    }
+    return STS_OK;
+}
+
+// group the state in buffer cur by the hash bucket of key & notmask; returns
+// the buffer that holds the sorted terms and the bucket bits used
+sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
+{
+    const u64 nb = std::max<u64>(c->n_bound, 2);
+    int lg = 0;
+    while ((1ull << lg) < nb && lg < 63) ++lg;
+    int npass = (lg + 7) / 8;
+    npass = std::min(std::max(npass, 1), STS_MAX_PASSES);
+    const int hb = 8 * npass;
+    const int grid = (int)std::min<u64>(std::max<u64>(ceil_div(nb, STS_WG * 8), 1), 1024);
+    STS_LAUNCH(c, STS_K_RADIX_HIST, launch_radix_hist(c->keys[c->cur], &c->ctl->cnt[c->cur], notmask, hb, npass, c->rhist, grid,
+                                 c->stream));
+    STS_LAUNCH(c, STS_K_RADIX_SCAN, launch_radix_scan(c->rhist, c->roffs, npass, c->stream));
+    const int tiles = (int)std::max<u64>(ceil_div(nb, STS_TILE), 1);
+    const int a = (c->cur + 1) % 3, b = (c->cur + 2) % 3;
+    int src = c->cur, dst = a;
+    for (int p = 0; p < npass; ++p) {
+        const int shift = 64 - hb + 8 * p;
+        STS_LAUNCH(c, STS_K_RADIX_PASS, launch_radix_pass(c->prec, c->keys[src], c->amps[src], c->keys[dst], c->amps[dst],
+                                     &c->ctl->cnt[src], &c->ctl->cnt[dst], notmask, shift, c->roffs + 256 * p,
+                                     c->look_radix + (u64)p * c->tiles_cap * 256, c->tctr + p, next_epoch(c),
+                                     tiles, c->stream));
+        src = dst;
+        dst = dst == a ? b : a;
+    }
+    *sorted = src;
+    *hb_out = hb;
+    return STS_OK;
+}
+
+// number of nonzero candidates of the pending gate (synchronises)
+sts_status count_candidates(sts_ctx *c, u64 *count)
+{
+    PassBufs b = pass_bufs(c, c->cur, -1);
+    const int G = hist_groups(c->n_bound);
+    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, c->stream));
+    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, c->stream));
+    const sts_status st = sync_ctl(c);
+    if (st != STS_OK) return st;
+    *count = c->hctl->cand_all;
+    return STS_OK;
+}
+
+// write out the pending gate's candidates without truncation
+sts_status materialise(sts_ctx *c)
+{
+    if (!c->pending) return STS_OK;
+    const u64 cb = sat_shl(c->n_bound, c->gate.m);
+    u64 bound = cb;
+    if (cb > c->cap) {
+        u64 count = 0;
+        const sts_status st = count_candidates(c, &count);
+        if (st != STS_OK) return st;
+        if (count > c->cap) {
+            c->pending = false; // drop the gate: the sorted input is the state before it
+            return STS_E_CAPACITY;
+        }
+        bound = count;
+    }
+    const int dst = (c->cur + 1) % 3;
+    PassBufs b = pass_bufs(c, c->cur, dst);
+    b.materialise = 1;
+    b.epoch = next_epoch(c);
+    STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_compact(c->prec, STS_KIND_EMIT, c->gate, b, compact_tiles(c->n_bound), c->stream));
+    c->cur = dst;
+    c->n_bound = std::min(bound, c->cap);
+    c->pending = false;
+    return STS_OK;
+}
+
+GateArg identity_gate()
+{
+    GateArg g;
+    std::memset(&g, 0, sizeof(g));
+    g.m = 0;
+    g.notmask = ~0ull;
+    return g;
+}
+
+sts_status check_live(sts_ctx *c)
+{
+    if (!c) return STS_E_ARG;
+    if (c->poisoned) return STS_E_STATE;
+    return STS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+sts_status sts_required_bytes(uint64_t cap_terms, int precision, size_t *bytes)
+{
+    if (!bytes || cap_terms == 0 || (precision != STS_C128 && precision != STS_C64)) return STS_E_ARG;
+    if (cap_terms > (1ull << 36)) return STS_E_ARG;
+    *bytes = (size_t)make_layout(cap_terms, precision).total;
+    return STS_OK;
+}
+
+sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass, int precision, void *hip_stream,
+                    void *arena, size_t arena_bytes, uint64_t cap_terms)
+{
+    if (!out) return STS_E_ARG;
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 64) return STS_E_ARG;
+    if (precision != STS_C128 && precision != STS_C64) return STS_E_ARG;
+    if (!(mass == mass)) return STS_E_ARG; // NaN
+    if (arena && arena_bytes == 0) return STS_E_ARG;
+    if (cap_terms > (1ull << 36)) return STS_E_ARG;
+    u64 cap = cap_terms;
+    if (arena) {
+        if (cap == 0) {
+            // largest capacity whose layout fits the arena
+            u64 lo = 1, hi = 1ull << 36;
+            if (make_layout(1, precision).total > arena_bytes) return STS_E_NOMEM;
+            while (lo < hi) {
+                const u64 mid = lo + (hi - lo + 1) / 2;
+                if (make_layout(mid, precision).total <= arena_bytes) lo = mid;
+                else hi = mid - 1;
+            }
+            cap = lo;
+        }
+        if (make_layout(cap, precision).total > arena_bytes) return STS_E_NOMEM;
+    } else if (cap == 0) {
+        cap = std::max<u64>(max_terms, 1ull << 20);
+    }
+    if (max_terms > cap) return STS_E_CAPACITY;
+
+    sts_ctx *c = new (std::nothrow) sts_ctx();
+    if (!c) return STS_E_NOMEM;
+    c->n_qubits = n_qubits;
+    c->prec = precision;
+    c->K = max_terms;
+    c->p = (mass > 0.0 && mass < 1.0) ? mass : 0.0;
+    c->stream = (hipStream_t)hip_stream;
+    c->cap = cap;
+    c->scap = 4 * cap;
+    c->tiles_cap = ceil_div(cap, STS_TILE);
+    c->gtiles_cap = ceil_div(cap, STS_GTILE);
+    const Layout L = make_layout(cap, precision);
+    if (arena) {
+        c->mem = (unsigned char *)arena;
+    } else {
+        void *p = nullptr;
+        const hipError_t e = hipMalloc(&p, L.total);
+        if (e != hipSuccess) {
+            delete c;
+            return e == hipErrorOutOfMemory ? STS_E_NOMEM : STS_E_HIP;
+        }
+        c->mem = (unsigned char *)p;
+        c->own_mem = true;
+    }
+    c->ctl = (DevCtl *)(c->mem + L.ctl);
+    for (int i = 0; i < 3; ++i) {
+        c->keys[i] = (u64 *)(c->mem + L.keys[i]);
+        c->amps[i] = c->mem + L.amps[i];
+    }
+    c->side_key = (u64 *)(c->mem + L.side_key);
+    c->side_w = (u64 *)(c->mem + L.side_w);
+    c->h1 = (u64 *)(c->mem + L.h1);
+    c->h2 = (u64 *)(c->mem + L.h2);
+    c->best = (u64 *)(c->mem + L.best);
+    c->rhist = (u64 *)(c->mem + L.rhist);
+    c->roffs = (u64 *)(c->mem + L.roffs);
+    c->look_radix = (u64 *)(c->mem + L.look_radix);
+    c->look_comp = (u64 *)(c->mem + L.look_comp);
+    c->tctr = (u32 *)(c->mem + L.tctr);
+    c->dU = (double *)(c->mem + L.dU);
+
+    hipError_t e = hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hU, kULen * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->u_event, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        sts_free(c);
+        return STS_E_HIP;
+    }
+    std::memset(c->hctl, 0, sizeof(DevCtl));
+    c->hctl->K = c->K;
+    c->hctl->p = c->p;
+    c->hctl->scale = 1.0;
+    c->hctl->frac = 1.0;
+    // zero the bookkeeping regions (everything but the term buffers)
+    e = hipMemsetAsync(c->mem + L.h1, 0, L.total - L.h1, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->ctl, c->hctl, sizeof(DevCtl), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_init_state(precision, c->keys[0], c->amps[0], &c->ctl->cnt[0], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        sts_free(c);
+        return e == hipErrorOutOfMemory ? STS_E_NOMEM : STS_E_HIP;
+    }
+    c->cur = 0;
+    c->n_bound = 1;
+    *out = c;
+    return STS_OK;
+}
+
+sts_status sts_apply_gate(sts_ctx *c, int m, const int *qubits, const double *U)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (!qubits || !U || m < 1 || m > STS_MAXM || m > c->n_qubits) return STS_E_ARG;
+    u64 mask = 0;
+    for (int t = 0; t < m; ++t) {
+        if (qubits[t] < 0 || qubits[t] >= c->n_qubits) return STS_E_ARG;
+        if (mask & (1ull << qubits[t])) return STS_E_ARG;
+        mask |= 1ull << qubits[t];
+    }
+    for (int i = 0; i < 2 << (2 * m); ++i)
+        if (!std::isfinite(U[i])) return STS_E_ARG;
+    st = materialise(c);
+    if (st != STS_OK) return st;
+
+    GateArg g;
+    std::memset(&g, 0, sizeof(g));
+    g.m = m;
+    for (int t = 0; t < m; ++t) g.q[t] = qubits[t];
+    g.notmask = ~mask;
+    const int dim = 1 << m;
+    if (m <= 3) {
+        for (int i = 0; i < dim * dim; ++i) {
+            g.ur[i] = U[2 * i];
+            g.ui[i] = U[2 * i + 1];
+        }
+    } else {
+        // the previous copy from the staging buffer must have finished
+        if (c->u_event_live) STS_TRY(c, hipEventSynchronize(c->u_event));
+        std::memcpy(c->hU, U, (size_t)2 * dim * dim * sizeof(double));
+        STS_TRY(c, hipMemcpyAsync(c->dU, c->hU, (size_t)2 * dim * dim * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+        STS_TRY(c, hipEventRecord(c->u_event, c->stream));
+        c->u_event_live = true;
+        g.uptr = c->dU;
+    }
+    int sorted = c->cur, hb = 8;
+    st = sort_state(c, g.notmask, &sorted, &hb);
+    if (st != STS_OK) return st;
+    g.hb = hb;
+    c->cur = sorted;
+    c->gate = g;
+    c->pending = true;
+    return STS_OK;
+}
+
+sts_status sts_truncate(sts_ctx *c)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (!c->pending) {
+        c->gate = identity_gate();
+        c->pending = true;
+    }
+    const u64 cb = sat_shl(c->n_bound, c->gate.m);
+    const int out = (c->cur + 1) % 3;
+    PassBufs b = pass_bufs(c, c->cur, out);
+    const int G = hist_groups(c->n_bound);
+    const int tiles = compact_tiles(c->n_bound);
+    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, c->stream));
+    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, c->stream));
+    b.epoch = next_epoch(c);
+    STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_compact(c->prec, STS_KIND_EXTRACT, c->gate, b, tiles, c->stream));
+    const int sg = (int)std::min<u64>(std::max<u64>(ceil_div(std::min(cb, c->scap), 256), 1), STS_SIDE_GROUPS);
+    STS_LAUNCH(c, STS_K_SIDE_HIST, launch_side_hist(b, c->h2, sg, c->stream));
+    STS_LAUNCH(c, STS_K_FINAL, launch_final(b, c->stream));
+    u64 nb = c->K ? std::min<u64>(c->K, cb) : cb;
+    if (nb > c->cap) {
+        // only p-mass limits this cut: learn its size before writing
+        st = sync_ctl(c);
+        if (st != STS_OK) return st;
+        const u64 L = c->hctl->keep_all ? c->hctl->n_cand : c->hctl->L;
+        if (L > c->cap) {
+            c->pending = false;
+            return STS_E_CAPACITY;
+        }
+        nb = L;
+    }
+    b.epoch = next_epoch(c);
+    STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_compact(c->prec, STS_KIND_EMIT, c->gate, b, tiles, c->stream));
+    c->cur = out;
+    c->n_bound = nb;
+    c->pending = false;
+    return STS_OK;
+}
+
+sts_status sts_peak(sts_ctx *c, uint64_t *key, double *prob)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (!key || !prob) return STS_E_ARG;
+    st = materialise(c);
+    if (st != STS_OK) return st;
+    const GateArg g = identity_gate();
+    PassBufs b = pass_bufs(c, c->cur, -1);
+    const int G = hist_groups(c->n_bound);
+    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, g, b, G, c->stream));
+    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, c->stream));
+    st = sync_ctl(c);
+    if (st != STS_OK) return st;
+    if (c->hctl->cnt[c->cur] == 0) return STS_E_STATE;
+    *key = c->hctl->peak_key;
+    *prob = c->hctl->peak_w / c->hctl->peak_W;
+    return STS_OK;
+}
+
+sts_status sts_num_terms(sts_ctx *c, uint64_t *n)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (!n) return STS_E_ARG;
+    st = materialise(c);
+    if (st != STS_OK) return st;
+    st = sync_ctl(c);
+    if (st != STS_OK) return st;
+    *n = c->hctl->cnt[c->cur];
+    c->n_bound = *n;
+    return STS_OK;
+}
+
+sts_status sts_read_terms(sts_ctx *c, uint64_t cap, uint64_t *keys, double *amps, uint64_t *n)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (!n || (cap && (!keys || !amps))) return STS_E_ARG;
+    st = sts_num_terms(c, n);
+    if (st != STS_OK) return st;
+    const u64 cnt = *n;
+    if (cnt > cap) return STS_E_CAPACITY;
+    if (cnt == 0) return STS_OK;
+    std::vector<u64> k(cnt);
+    STS_TRY(c, hipMemcpyAsync(k.data(), c->keys[c->cur], cnt * 8, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> a(2 * cnt);
+    std::vector<float> af;
+    if (c->prec == STS_C128) {
+        STS_TRY(c, hipMemcpyAsync(a.data(), c->amps[c->cur], cnt * 16, hipMemcpyDeviceToHost, c->stream));
+    } else {
+        af.resize(2 * cnt);
+        STS_TRY(c, hipMemcpyAsync(af.data(), c->amps[c->cur], cnt * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    STS_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->prec == STS_C64)
+        for (u64 i = 0; i < 2 * cnt; ++i) a[i] = (double)af[i];
+    std::vector<u64> order(cnt);
+    for (u64 i = 0; i < cnt; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](u64 x, u64 y) { return k[x] < k[y]; });
+    for (u64 i = 0; i < cnt; ++i) {
+        keys[i] = k[order[i]];
+        amps[2 * i] = a[2 * order[i]];
+        amps[2 * i + 1] = a[2 * order[i] + 1];
+    }
+    return STS_OK;
+}
+
+sts_status sts_load_terms(sts_ctx *c, uint64_t n, const uint64_t *keys, const double *amps)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (n && (!keys || !amps)) return STS_E_ARG;
+    if (n > c->cap) return STS_E_CAPACITY;
+    const u64 lim = c->n_qubits == 64 ? ~0ull : ((1ull << c->n_qubits) - 1);
+    std::vector<u64> sk(keys, keys + n);
+    for (u64 i = 0; i < n; ++i)
+        if (sk[i] > lim || !std::isfinite(amps[2 * i]) || !std::isfinite(amps[2 * i + 1])) return STS_E_ARG;
+    std::sort(sk.begin(), sk.end());
+    for (u64 i = 1; i < n; ++i)
+        if (sk[i] == sk[i - 1]) return STS_E_ARG;
+    // the state is replaced: any pending gate is dropped
+    c->pending = false;
+    if (n) {
+        STS_TRY(c, hipMemcpyAsync(c->keys[c->cur], keys, n * 8, hipMemcpyHostToDevice, c->stream));
+        if (c->prec == STS_C128) {
+            STS_TRY(c, hipMemcpyAsync(c->amps[c->cur], amps, n * 16, hipMemcpyHostToDevice, c->stream));
+            STS_TRY(c, hipStreamSynchronize(c->stream));
+        } else {
+            std::vector<float> af(2 * n);
+            for (u64 i = 0; i < 2 * n; ++i) af[i] = (float)amps[i];
+            STS_TRY(c, hipMemcpyAsync(c->amps[c->cur], af.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+            STS_TRY(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    STS_TRY(c, launch_set_n(&c->ctl->cnt[c->cur], n, c->stream));
+    c->n_bound = n;
+    return STS_OK;
+}
+
+sts_status sts_stats(sts_ctx *c, double *W, double *kept_fraction, double *log10_cum_kept, uint64_t *last_candidates)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    st = sync_ctl(c);
+    if (st != STS_OK) return st;
+    if (W) *W = c->hctl->W;
+    if (kept_fraction) *kept_fraction = c->hctl->frac;
+    if (log10_cum_kept) *log10_cum_kept = c->hctl->log10_cum;
+    if (last_candidates) *last_candidates = c->hctl->n_cand;
+    return STS_OK;
+}
+
+sts_status sts_counters(sts_ctx *c, uint64_t *gate_steps, uint64_t *term_updates, uint64_t *candidates)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    st = sync_ctl(c);
+    if (st != STS_OK) return st;
+    if (gate_steps) *gate_steps = c->hctl->tot_steps;
+    if (term_updates) *term_updates = c->hctl->tot_updates;
+    if (candidates) *candidates = c->hctl->tot_cand;
+    return STS_OK;
+}
+
+sts_status sts_profile(sts_ctx *c, int enable)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    c->prof = enable != 0;
+    return STS_OK;
+}
+
+sts_status sts_kernel_time(sts_ctx *c, int kind, int reset, double *total_ms, uint64_t *launches)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (kind < 0 || kind >= STS_K_COUNT) return STS_E_ARG;
+    STS_TRY(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    if (total_ms) *total_ms = c->prof_ms[kind];
+    if (launches) *launches = c->prof_n[kind];
+    if (reset) {
+        for (int k = 0; k < STS_K_COUNT; ++k) {
+            c->prof_ms[k] = 0;
+            c->prof_n[k] = 0;
+        }
+    }
+    return STS_OK;
+}
+
+void sts_free(sts_ctx *c)
+{
+    if (!c) return;
+    if (c->stream || c->mem) (void)hipStreamSynchronize(c->stream);
+    for (auto &m : c->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->own_mem && c->mem) (void)hipFree(c->mem);
+    if (c->hctl) (void)hipHostFree(c->hctl);
+    if (c->hU) (void)hipHostFree(c->hU);
+    if (c->u_event) (void)hipEventDestroy(c->u_event);
+    delete c;
+}
+
+const char *sts_strerror(sts_status s)
+{
+    switch (s) {
+    case STS_OK: return "ok";
+    case STS_E_ARG: return "invalid argument";
+    case STS_E_NOMEM: return "device allocation failed";
+    case STS_E_CAPACITY: return "result exceeds the context's capacity";
+    case STS_E_HIP: return "HIP runtime error";
+    case STS_E_STATE: return "context poisoned or call out of order";
+    }
+    return "unknown status";
+}
+
+} // extern "C"

@@ -1,0 +1,395 @@
+// common.h - device-side definitions shared by the library's kernels.
+//
+// Layout of a state in HBM: structure-of-arrays, keys u64[cap] and amplitudes
+// (double2 or float2)[cap], so every pass streams two coalesced arrays. The
+// term count lives in the device control block (DevCtl), never on the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+typedef unsigned __int128 u128;
+
+#define STS_WG 256            // threads per workgroup in the streaming kernels
+#define STS_NBIN 2048         // histogram bins per selection level
+#define STS_NL 20             // 64-bit limbs of the exact mass accumulator
+#define STS_SMALL 4096        // a subset this small is sorted in LDS
+#define STS_MAXM 5            // largest gate (qubits)
+#define STS_MAX_PASSES 4      // radix passes per sort (8-bit digits)
+#define STS_TILE_ITEMS 16     // keys per thread in a radix tile
+#define STS_TILE (STS_WG * STS_TILE_ITEMS)
+
+// --------------------------------------------------------------------------
+// exact masses: an unsigned integer count of 2^-1074 units (every binary64
+// value is such a multiple), STS_NL limbs, little-endian
+// --------------------------------------------------------------------------
+struct Big {
+    u64 l[STS_NL];
+};
+
+// decision state of a truncation and the running statistics (one per state)
+struct DevCtl {
+    u64 cnt[4];          // terms held by each term buffer (slot 3 unused)
+    u64 n_cand;          // candidates of the last truncation (from the first pass)
+    u64 cand_all;        // candidates counted by the last level-1 pass of any kind
+    u64 tot_steps;       // truncations run since init
+    u64 tot_updates;     // input terms of those truncations
+    u64 tot_cand;        // candidates of those truncations
+    u64 side_n;          // candidates copied to the side buffer
+    u32 done[4];         // last-workgroup counters, one per kernel kind
+    u32 flags;           // STS_F_* below
+    u32 pad0;
+    // truncation rule
+    u64 K;               // top-k (0 = off)
+    double p;            // p-mass (off unless 0 < p < 1)
+    // decision
+    int keep_all;        // the rule keeps every candidate
+    int dropped;         // L < C: rescale
+    int e_star;          // exponent field of the level holding the L-th term
+    int level;           // last resolved level
+    u64 cnt_before;      // terms ranked before the current subset
+    u64 mb_lo, mb_hi;    // mantissa sum (units 2^(max(e*,1)-1075)) ranked before the subset inside e*
+    u64 R_lo, R_hi;      // remaining mass to reach, same units; all ones = off
+    u64 sub_count;       // terms in the current subset
+    u64 vpre_hi, vpre_lo;// fixed high part of the within-exponent rank key
+    int vshift;          // bits of the rank key below the fixed part
+    int pad1;
+    u64 L;               // terms kept
+    u64 thr_wbits, thr_key; // the L-th term in rank order
+    double scale;        // renormalisation factor (1 when nothing dropped)
+    double S;            // kept mass (correctly rounded)
+    double W;            // total mass before the cut (correctly rounded)
+    double frac;         // S / W
+    double log10_cum;    // running sum of log10(frac)
+    u64 peak_key;
+    double peak_w;
+    double peak_W;       // exact total of the state the peak was taken on, rounded
+    Big S_excl;          // exact mass of the bins above e*
+    Big T;               // exact p * W target (rounded up)
+};
+
+#define STS_F_SIDE_OVERFLOW 1u
+#define STS_F_OUT_OVERFLOW 2u
+#define STS_F_UNRESOLVED 4u
+#define STS_F_INEXACT 8u
+
+// --------------------------------------------------------------------------
+// hashing: a bijective 64-bit mixer (splitmix64 finalisation). Equal hashes
+// mean equal inputs, so grouping by hash buckets never merges distinct keys.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ u64 sts_mix64(u64 x)
+{
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+// weight bits: |a|^2 = fl64(fl64(re*re) + fl64(im*im)), components in FP64
+__device__ __forceinline__ double sts_weight(double re, double im)
+{
+    return re * re + im * im;
+}
+
+__device__ __forceinline__ u64 sts_dbits(double x) { return (u64)__double_as_longlong(x); }
+
+// mantissa as an integer and the exponent of its unit: w = mant * 2^(max(e,1) - 1075)
+__device__ __forceinline__ u64 sts_mant(u64 wbits)
+{
+    const u64 e = wbits >> 52;
+    const u64 f = wbits & ((1ull << 52) - 1);
+    return e ? (f | (1ull << 52)) : f;
+}
+
+// --------------------------------------------------------------------------
+// Big helpers (single-thread use)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void big_zero(Big &a)
+{
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i) a.l[i] = 0;
+}
+
+// a += v * 2^bit, v < 2^128 (given as lo, hi). Every limb index is a
+// compile-time constant, so the accumulator stays in registers.
+__device__ inline void big_add_shifted(Big &a, u64 vlo, u64 vhi, int bit)
+{
+    const int limb = bit >> 6, off = bit & 63;
+    const u64 p0 = vlo << off;
+    const u64 p1 = off ? ((vhi << off) | (vlo >> (64 - off))) : vhi;
+    const u64 p2 = off ? (vhi >> (64 - off)) : 0;
+    u64 carry = 0;
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i) {
+        const int k = i - limb;
+        const u64 add = k == 0 ? p0 : (k == 1 ? p1 : (k == 2 ? p2 : 0));
+        const u64 s = a.l[i] + add;
+        const u64 c1 = s < add;
+        const u64 s2 = s + carry;
+        const u64 c2 = s2 < s;
+        a.l[i] = s2;
+        carry = c1 + c2;
+    }
+}
+
+__device__ inline void big_add(Big &a, const Big &b)
+{
+    u64 carry = 0;
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i) {
+        const u64 s = a.l[i] + b.l[i];
+        const u64 c1 = s < b.l[i];
+        const u64 s2 = s + carry;
+        const u64 c2 = s2 < s;
+        a.l[i] = s2;
+        carry = c1 + c2;
+    }
+}
+
+// a -= b (requires a >= b)
+__device__ inline void big_sub(Big &a, const Big &b)
+{
+    u64 borrow = 0;
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i) {
+        const u64 x = a.l[i];
+        const u64 d = x - b.l[i];
+        const u64 b1 = x < b.l[i];
+        const u64 d2 = d - borrow;
+        const u64 b2 = d < borrow;
+        a.l[i] = d2;
+        borrow = b1 | b2;
+    }
+}
+
+__device__ inline int big_cmp(const Big &a, const Big &b)
+{
+    int r = 0;
+#pragma unroll
+    for (int i = STS_NL - 1; i >= 0; --i) {
+        if (r == 0 && a.l[i] != b.l[i]) r = a.l[i] < b.l[i] ? -1 : 1;
+    }
+    return r;
+}
+
+__device__ inline bool big_is_zero(const Big &a)
+{
+    u64 o = 0;
+    for (int i = 0; i < STS_NL; ++i) o |= a.l[i];
+    return o == 0;
+}
+
+// r = ceil(a * m / 2^s)
+__device__ inline void big_mul_shr_ceil(Big &r, const Big &a, u64 m, int s)
+{
+    Big prod;
+    u64 carry = 0;
+    for (int i = 0; i < STS_NL; ++i) {
+        const u128 t = (u128)a.l[i] * m + carry;
+        prod.l[i] = (u64)t;
+        carry = (u64)(t >> 64);
+    }
+    const int wl = s >> 6, wb = s & 63;
+    bool any = false;
+    for (int i = 0; i < wl && i < STS_NL; ++i) any |= prod.l[i] != 0;
+    if (wl < STS_NL && wb) any |= (prod.l[wl] & ((1ull << wb) - 1)) != 0;
+    for (int i = 0; i < STS_NL; ++i) {
+        const int src = i + wl;
+        u64 v = 0;
+        if (src < STS_NL) {
+            v = prod.l[src] >> wb;
+            if (wb && src + 1 < STS_NL) v |= prod.l[src + 1] << (64 - wb);
+        }
+        r.l[i] = v;
+    }
+    if (any) big_add_shifted(r, 1, 0, 0);
+}
+
+// ceil(a / 2^s) clamped to 2^128 - 1 (returned as lo, hi)
+__device__ inline void big_shr_ceil_u128(const Big &a, int s, u64 &lo, u64 &hi)
+{
+    const int wl = s >> 6, wb = s & 63;
+    bool any = false;
+    for (int i = 0; i < wl && i < STS_NL; ++i) any |= a.l[i] != 0;
+    if (wl < STS_NL && wb) any |= (a.l[wl] & ((1ull << wb) - 1)) != 0;
+    u64 w[3];
+    for (int k = 0; k < 3; ++k) {
+        const int src = wl + k;
+        u64 v = 0;
+        if (src < STS_NL) {
+            v = a.l[src] >> wb;
+            if (wb && src + 1 < STS_NL) v |= a.l[src + 1] << (64 - wb);
+        }
+        w[k] = v;
+    }
+    bool big_hi = w[2] != 0;
+    for (int i = wl + 3; i < STS_NL; ++i) big_hi |= a.l[i] != 0;
+    if (big_hi) { lo = ~0ull; hi = ~0ull; return; }
+    lo = w[0];
+    hi = w[1];
+    if (any) {
+        lo += 1;
+        if (lo == 0) {
+            hi += 1;
+            if (hi == 0) { lo = ~0ull; hi = ~0ull; }
+        }
+    }
+}
+
+__device__ inline int big_top_bit(const Big &a)
+{
+    for (int i = STS_NL - 1; i >= 0; --i)
+        if (a.l[i]) return i * 64 + 63 - __clzll((long long)a.l[i]);
+    return -1;
+}
+
+__device__ inline int big_bit(const Big &a, int pos)
+{
+    if (pos < 0) return 0;
+    return (int)((a.l[pos >> 6] >> (pos & 63)) & 1);
+}
+
+__device__ inline bool big_any_below(const Big &a, int pos)
+{
+    if (pos <= 0) return false;
+    const int wl = pos >> 6, wb = pos & 63;
+    for (int i = 0; i < wl; ++i)
+        if (a.l[i]) return true;
+    return wb && (a.l[wl] & ((1ull << wb) - 1));
+}
+
+// nearest binary64 (ties to even)
+__device__ inline double big_to_double(const Big &a)
+{
+    const int h = big_top_bit(a);
+    if (h < 0) return 0.0;
+    if (h < 53) return ldexp((double)a.l[0], -1074);
+    int lo = h - 52;
+    u64 mant = 0;
+    for (int b = h; b >= lo; --b) mant = (mant << 1) | (u64)big_bit(a, b);
+    const int guard = big_bit(a, lo - 1);
+    const bool sticky = big_any_below(a, lo - 1);
+    if (guard && (sticky || (mant & 1))) {
+        mant += 1;
+        if (mant == (1ull << 53)) { mant >>= 1; lo += 1; }
+    }
+    return ldexp((double)mant, lo - 1074);
+}
+
+// --------------------------------------------------------------------------
+// wave64 / workgroup helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int sts_lane() { return __lane_id(); }
+
+__device__ __forceinline__ u64 sts_lanemask_lt() { return (1ull << sts_lane()) - 1ull; }
+
+// inclusive scan over the 64 lanes of a wave
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int lane = sts_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// exclusive scan over a workgroup of NT threads (NT/64 waves); returns the
+// exclusive prefix and writes the total to *total. scratch: NT/64 entries.
+template <typename T, int NT>
+__device__ __forceinline__ T block_excl_scan(T v, T *scratch, T *total)
+{
+    const int lane = sts_lane();
+    const int w = threadIdx.x >> 6;
+    T inc = wave_incl_scan(v);
+    if (lane == 63) scratch[w] = inc;
+    __syncthreads();
+    T base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const T s = scratch[i];
+        if (i < w) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// "last workgroup" election: every workgroup calls this once after its global
+// atomics; it returns true in exactly one workgroup (the last to arrive),
+// which then sees every other workgroup's atomics. Resets the counter.
+__device__ inline bool sts_last_block(u32 *counter, u32 *s_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const u32 prev = atomicAdd(counter, 1u);
+        const bool last = prev == gridDim.x - 1;
+        if (last) st_agent(counter, 0u);
+        *s_flag = last ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool last = *s_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// --------------------------------------------------------------------------
+// decoupled look-back words: epoch (24 bits) | status (2) | value (38).
+// The epoch tags the launch that wrote a word, so the arrays never need
+// clearing between launches. status 1 = tile aggregate, 2 = inclusive prefix.
+// --------------------------------------------------------------------------
+#define STS_LB_VBITS 38
+#define STS_LB_VMASK ((1ull << STS_LB_VBITS) - 1ull)
+
+__device__ __forceinline__ u64 lb_pack(u32 epoch, u32 status, u64 val)
+{
+    return ((u64)(epoch & 0xffffffu) << 40) | ((u64)status << STS_LB_VBITS) | (val & STS_LB_VMASK);
+}
+
+// Publish this tile's aggregate, walk back over predecessors until an
+// inclusive prefix is found, publish the inclusive prefix. Returns the
+// exclusive prefix. Tiles are numbered in the order their workgroups started,
+// so every predecessor is resident or finished and the wait ends.
+__device__ inline u64 lb_exclusive(u64 *look, u64 stride, u64 tile, u64 local, u32 epoch)
+{
+    const u32 ep = epoch & 0xffffffu;
+    if (tile == 0) {
+        st_agent(&look[0], lb_pack(epoch, 2, local));
+        return 0;
+    }
+    st_agent(&look[tile * stride], lb_pack(epoch, 1, local));
+    u64 excl = 0;
+    u64 j = tile - 1;
+    while (true) {
+        const u64 v = ld_agent(&look[j * stride]);
+        if ((u32)(v >> 40) != ep) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += v & STS_LB_VMASK;
+        if (((v >> STS_LB_VBITS) & 3u) == 2u) break;
+        --j;
+    }
+    st_agent(&look[tile * stride], lb_pack(epoch, 2, excl + local));
+    return excl;
+}

@@ -1,0 +1,69 @@
+// kernels.h - launchers for the library's kernels (host side) and the
+// argument blocks they take. Everything here is internal to libsts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+// Gate description passed by value to the grouping kernels. For m <= 3 the
+// matrix travels in the argument block itself (no device copy per gate);
+// for m = 4, 5 it is read from uptr (device, interleaved re/im).
+struct GateArg {
+    int m;
+    int q[STS_MAXM];
+    u64 notmask;        // ~(sum of 2^q)
+    int hb;             // hash-bucket bits the input was sorted by (m >= 1)
+    int pad;
+    double ur[64];      // row-major U, real parts (m <= 3)
+    double ui[64];      // imaginary parts
+    const double *uptr; // m >= 4
+};
+
+// Device buffers a grouping pass reads and writes.
+struct PassBufs {
+    const u64 *keys;      // sorted input keys (or the state, m = 0)
+    const void *amps;     // sorted input amplitudes
+    const u64 *n_in;      // number of input terms (device)
+    u64 *n_out;           // number of terms written to out_keys/out_amps (device)
+    DevCtl *ctl;
+    // level-1 histogram (per exponent field) and per-workgroup best term
+    u64 *h1;              // [3][STS_NBIN]: count, mantissa>>26, mantissa & (2^26-1)
+    u64 *best;            // [2][max groups]: (wbits | 2^63), key
+    // compaction targets
+    u64 *side_key;        // side buffer: candidates of the exponent holding the cut
+    u64 *side_w;
+    u64 side_cap;
+    u64 *out_keys;        // new state
+    void *out_amps;
+    u64 out_cap;
+    u64 *look;            // look-back words, one per tile
+    u32 *tile_ctr;
+    u32 epoch;            // tags look-back words of this launch
+    int materialise;      // 1: keep every candidate, no rescale (no truncation)
+};
+
+// launch helpers (return hipError_t of the launch)
+hipError_t launch_radix_hist(const u64 *keys, const u64 *n_in, u64 notmask, int hb, int npass,
+                             u64 *hist, int grid, hipStream_t s);
+hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, hipStream_t s);
+hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout,
+                             const u64 *n_in, u64 *n_out, u64 notmask, int shift, const u64 *offs,
+                             u64 *look, u32 *tile_ctr, u32 epoch, int tiles, hipStream_t s);
+
+hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, hipStream_t s);
+hipError_t launch_group_compact(int prec, int kind, const GateArg &g, const PassBufs &b, int tiles,
+                                hipStream_t s);
+hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, hipStream_t s);
+hipError_t launch_side_hist(const PassBufs &b, u64 *h2, int grid, hipStream_t s);
+hipError_t launch_final(const PassBufs &b, hipStream_t s);
+hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s);
+hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s);
+
+#define STS_KIND_EXTRACT 0
+#define STS_KIND_EMIT 1
+#define STS_GROUP_ITEMS 4                       // elements per thread in a compaction tile
+#define STS_GTILE (STS_WG * STS_GROUP_ITEMS)     // elements per compaction tile
+#define STS_MAX_GROUPS 1024                      // persistent grid of the histogram pass
+#define STS_SIDE_GROUPS 512

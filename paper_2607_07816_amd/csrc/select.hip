@@ -1,0 +1,616 @@
+// select.hip - finding the cut of a truncation exactly.
+//
+// Truncation keeps the shortest prefix of the terms ranked by (|a|^2
+// descending, key ascending) that holds at least p of the mass, and at most K
+// terms (Sec. III; the ranking by decreasing |a|^2 of Sec. IV.B). Instead of
+// sorting all candidates, the cut is located by most-significant-digit
+// selection on the rank:
+//   level 1  - the exponent field of |a|^2 (2048 bins, from the histogram
+//              pass over the recomputed candidates),
+//   level 2  - within that exponent, the top 11 bits of the within-exponent
+//              rank key V = ((2^52 - 1 - fraction) << 64) | key, from the side
+//              buffer of that exponent's candidates,
+//   level 3+ - further 11-bit digits of V inside one workgroup, until at most
+//              4096 terms remain; those are sorted in LDS.
+// Masses are exact: each bin carries the exact integer sum of its weights'
+// mantissas, levels >= 2 share one exponent, and level 1 prefixes are exact
+// integers on the 2^-1074 grid. Every decision therefore equals the one made
+// in exact arithmetic, and the kept mass S is correctly rounded.
+#include "kernels.h"
+
+namespace {
+
+// bit position of the unit 2^(max(e,1)-1075) on the 2^-1074 grid
+__device__ __forceinline__ int unit_bit(int e) { return (e > 0 ? e : 1) - 1; }
+
+__device__ __forceinline__ u128 make128(u64 lo, u64 hi) { return ((u128)hi << 64) | lo; }
+
+// ---------------------------------------------------------------------------
+// level 1: one workgroup of 256 threads. Thread t owns the eight exponent
+// bins 2047-8t .. 2040-8t (descending weight order).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_only)
+{
+    __shared__ Big s_big[256];
+    __shared__ u64 s_cnt[256];
+    __shared__ Big s_T;
+    __shared__ u32 s_hit;
+    __shared__ u64 s_bw[4], s_bk[4];
+    const int t = threadIdx.x;
+    DevCtl *ctl = b.ctl;
+    u64 *h1 = b.h1;
+
+    // own bins
+    u64 c[8];
+    u128 ms[8];
+    Big chunk;
+    big_zero(chunk);
+    u64 ccount = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int e = 2047 - 8 * t - k;
+        c[k] = h1[e];
+        ms[k] = ((u128)h1[STS_NBIN + e] << 26) + (u128)h1[2 * STS_NBIN + e];
+        ccount += c[k];
+        if (c[k]) big_add_shifted(chunk, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
+    }
+    // inclusive scans (Hillis-Steele) of the chunk masses and counts
+    s_big[t] = chunk;
+    s_cnt[t] = ccount;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        Big o;
+        u64 oc = 0;
+        const bool take = t >= d;
+        if (take) {
+            o = s_big[t - d];
+            oc = s_cnt[t - d];
+        }
+        __syncthreads();
+        if (take) {
+            big_add(chunk, o);
+            ccount += oc;
+            s_big[t] = chunk;
+            s_cnt[t] = ccount;
+        }
+        __syncthreads();
+    }
+    // chunk / ccount now inclusive; exclusive = inclusive - own
+    const u64 total_c = s_cnt[255];
+    if (t == 0) {
+        Big W = s_big[255];
+        const double Wd = big_to_double(W);
+        ctl->cand_all = total_c;
+        if (peak_only) {
+            ctl->peak_W = Wd;
+        } else {
+            ctl->W = Wd;
+            ctl->n_cand = total_c;
+            ctl->tot_steps += 1;
+            ctl->tot_updates += *b.n_in;
+            ctl->tot_cand += total_c;
+            const double p = ctl->p;
+            if (p > 0.0 && p < 1.0) {
+                const u64 pb = sts_dbits(p);
+                const u64 pe = pb >> 52, pf = pb & ((1ull << 52) - 1);
+                const u64 pm = pe ? (pf | (1ull << 52)) : pf;
+                const int sh = pe ? (int)(1075 - pe) : 1074;
+                Big T;
+                big_mul_shr_ceil(T, W, pm, sh);
+                s_T = T;
+                ctl->T = T;
+            }
+        }
+        s_hit = 0xffffffffu;
+    }
+    // peak: reduce the per-workgroup bests
+    {
+        u64 bw = 0, bk = ~0ull;
+        for (int i = t; i < groups; i += 256) {
+            const u64 w = b.best[i], k = b.best[STS_MAX_GROUPS + i];
+            if (w > bw || (w == bw && k < bk)) {
+                bw = w;
+                bk = k;
+            }
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            const u64 ow = __shfl_xor(bw, d, 64);
+            const u64 ok = __shfl_xor(bk, d, 64);
+            if (ow > bw || (ow == bw && ok < bk)) {
+                bw = ow;
+                bk = ok;
+            }
+        }
+        if ((t & 63) == 0) {
+            s_bw[t >> 6] = bw;
+            s_bk[t >> 6] = bk;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        u64 w = s_bw[0], k = s_bk[0];
+        for (int i = 1; i < 4; ++i)
+            if (s_bw[i] > w || (s_bw[i] == w && s_bk[i] < k)) {
+                w = s_bw[i];
+                k = s_bk[i];
+            }
+        ctl->peak_key = k;
+        ctl->peak_w = (w >> 63) ? __longlong_as_double((long long)(w & ~(1ull << 63))) : 0.0;
+    }
+    if (peak_only) {
+        __syncthreads();
+        for (int i = t; i < 3 * STS_NBIN; i += 256) h1[i] = 0;
+        return;
+    }
+
+    // first bin (in rank order) where the rule is met
+    const u64 K = ctl->K;
+    const double p = ctl->p;
+    const bool p_on = p > 0.0 && p < 1.0;
+    Big S = chunk; // exclusive prefix: inclusive minus own bins
+    u64 cnt = ccount;
+    {
+        Big own;
+        big_zero(own);
+        u64 oc = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int e = 2047 - 8 * t - k;
+            if (c[k]) big_add_shifted(own, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
+            oc += c[k];
+        }
+        big_sub(S, own);
+        cnt -= oc;
+    }
+    u32 hit = 0xffffffffu;
+    Big S_hit;
+    u64 cnt_hit = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (hit == 0xffffffffu && c[k]) {
+            const int e = 2047 - 8 * t - k;
+            Big inc = S;
+            big_add_shifted(inc, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
+            const bool hk = K > 0 && cnt + c[k] >= K;
+            const bool hp = p_on && big_cmp(inc, s_T) >= 0;
+            if (hk || hp) {
+                hit = (u32)(8 * t + k);
+                S_hit = S;
+                cnt_hit = cnt;
+            } else {
+                S = inc;
+                cnt += c[k];
+            }
+        }
+    }
+    if (hit != 0xffffffffu) atomicMin(&s_hit, hit);
+    __syncthreads();
+    const u32 first = s_hit;
+    if (first == 0xffffffffu) {
+        if (t == 0) {
+            ctl->keep_all = 1;
+            ctl->dropped = 0;
+            ctl->L = total_c;
+            ctl->scale = 1.0;
+            ctl->S = ctl->W;
+            ctl->frac = 1.0;
+            ctl->level = 1;
+        }
+    } else if (hit == first) {
+        const int e = 2047 - (int)first;
+        const int k = (int)first - 8 * t;
+        ctl->keep_all = 0;
+        ctl->e_star = e;
+        ctl->cnt_before = cnt_hit;
+        ctl->S_excl = S_hit;
+        ctl->sub_count = c[k];
+        ctl->mb_lo = 0;
+        ctl->mb_hi = 0;
+        ctl->level = 1;
+        if (p_on) {
+            Big D = s_T;
+            big_sub(D, S_hit);
+            u64 lo, hi;
+            big_shr_ceil_u128(D, unit_bit(e), lo, hi);
+            ctl->R_lo = lo;
+            ctl->R_hi = hi;
+        } else {
+            ctl->R_lo = ~0ull;
+            ctl->R_hi = ~0ull;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < 3 * STS_NBIN; i += 256) h1[i] = 0;
+}
+
+// within-exponent rank key: ascending V = descending weight, then ascending key
+__device__ __forceinline__ u128 rank_key(u64 wbits, u64 key)
+{
+    const u64 frac = wbits & ((1ull << 52) - 1);
+    return ((u128)(((1ull << 52) - 1) - frac) << 64) | (u128)key;
+}
+
+__device__ __forceinline__ u64 mant_of_v(u128 v, int e)
+{
+    const u64 frac = ((1ull << 52) - 1) - (u64)(v >> 64);
+    return e ? (frac | (1ull << 52)) : frac;
+}
+
+// Subset of the rank order still holding the cut: the terms of exponent e*
+// whose rank key V has the high part vpre above bit vshift.
+struct Sub {
+    u64 cnt_before; // terms ranked before the subset
+    u128 mb;        // their mantissa sum inside e* (units 2^(max(e*,1)-1075))
+    u128 vpre;
+    int vshift;
+    u64 count;      // terms in the subset
+};
+
+__device__ inline void sub_load(Sub &s, const DevCtl *ctl)
+{
+    s.cnt_before = ctl->cnt_before;
+    s.mb = make128(ctl->mb_lo, ctl->mb_hi);
+    s.vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
+    s.vshift = ctl->vshift;
+    s.count = ctl->sub_count;
+}
+
+__device__ inline void sub_store(const Sub &s, DevCtl *ctl)
+{
+    ctl->cnt_before = s.cnt_before;
+    ctl->mb_lo = (u64)s.mb;
+    ctl->mb_hi = (u64)(s.mb >> 64);
+    ctl->vpre_lo = (u64)s.vpre;
+    ctl->vpre_hi = (u64)(s.vpre >> 64);
+    ctl->vshift = s.vshift;
+    ctl->sub_count = s.count;
+}
+
+// Pick the first digit (ascending = rank order) where the rule is met, over
+// 2048 bins held in (cnt[], hi[], lo[]) - global (agent loads) or LDS - by NT
+// threads, and narrow *sub to it. K, R: the rule (R all ones = no p-mass).
+// Returns false if no digit qualifies.
+template <int NT>
+__device__ bool pick_digit(const u64 *cntp, const u64 *hip_, const u64 *lop, bool agent, u64 K, u128 R, int dw,
+                           Sub *sub, u128 *s_m, u64 *s_c, u32 *s_hit)
+{
+    constexpr int PER = STS_NBIN / NT;
+    const int t = threadIdx.x;
+    u64 c[PER];
+    u128 ms[PER];
+    u64 cc = 0;
+    u128 mm = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int d = PER * t + k;
+        if (agent) {
+            c[k] = ld_agent(&cntp[d]);
+            ms[k] = ((u128)ld_agent(&hip_[d]) << 26) + (u128)ld_agent(&lop[d]);
+        } else {
+            c[k] = cntp[d];
+            ms[k] = ((u128)hip_[d] << 26) + (u128)lop[d];
+        }
+        cc += c[k];
+        mm += ms[k];
+    }
+    const u64 own_c = cc;
+    const u128 own_m = mm;
+    s_c[t] = cc;
+    s_m[t] = mm;
+    if (t == 0) *s_hit = 0xffffffffu;
+    __syncthreads();
+    for (int d = 1; d < NT; d <<= 1) {
+        u64 oc = 0;
+        u128 om = 0;
+        if (t >= d) {
+            oc = s_c[t - d];
+            om = s_m[t - d];
+        }
+        __syncthreads();
+        if (t >= d) {
+            cc += oc;
+            mm += om;
+            s_c[t] = cc;
+            s_m[t] = mm;
+        }
+        __syncthreads();
+    }
+    // exclusive prefix of this thread's bins, from the subset's start
+    u64 cnt = sub->cnt_before + (cc - own_c);
+    u128 m = sub->mb + (mm - own_m);
+    u32 hit = 0xffffffffu;
+    u64 cnt_hit = 0;
+    u128 m_hit = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (hit == 0xffffffffu && c[k]) {
+            const bool hk = K > 0 && cnt + c[k] >= K;
+            const bool hp = m + ms[k] >= R;
+            if (hk || hp) {
+                hit = (u32)(PER * t + k);
+                cnt_hit = cnt;
+                m_hit = m;
+            } else {
+                cnt += c[k];
+                m += ms[k];
+            }
+        }
+    }
+    if (hit != 0xffffffffu) atomicMin(s_hit, hit);
+    __syncthreads();
+    const u32 first = *s_hit;
+    if (first == 0xffffffffu) {
+        __syncthreads();
+        return false;
+    }
+    if (hit == first) {
+        const int k = (int)first - PER * t;
+        sub->vpre = (sub->vpre << dw) | (u128)first;
+        sub->vshift -= dw;
+        sub->cnt_before = cnt_hit;
+        sub->mb = m_hit;
+        sub->count = c[k];
+    }
+    __syncthreads();
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// level 2 over the side buffer (many workgroups), pick by the last one
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
+{
+    __shared__ u32 s_cnt[STS_NBIN];
+    __shared__ u64 s_hi[STS_NBIN];
+    __shared__ u64 s_lo[STS_NBIN];
+    __shared__ u128 s_m[256];
+    __shared__ u64 s_c[256];
+    __shared__ u32 s_hit, s_flag;
+    __shared__ Sub s_sub;
+    DevCtl *ctl = b.ctl;
+    if (ctl->keep_all) return;
+    for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
+        s_cnt[i] = 0;
+        s_hi[i] = 0;
+        s_lo[i] = 0;
+    }
+    __syncthreads();
+    const u64 n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
+    for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < n; i += (u64)gridDim.x * 256) {
+        const u64 wb = b.side_w[i];
+        const u64 vh = ((1ull << 52) - 1) - (wb & ((1ull << 52) - 1));
+        const u32 d = (u32)(vh >> 41);
+        const u64 mant = sts_mant(wb);
+        atomicAdd(&s_cnt[d], 1u);
+        atomicAdd(&s_hi[d], mant >> 26);
+        atomicAdd(&s_lo[d], mant & ((1ull << 26) - 1));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
+        const u32 c = s_cnt[i];
+        if (c) {
+            atomicAdd(&h2[i], (u64)c);
+            atomicAdd(&h2[STS_NBIN + i], s_hi[i]);
+            atomicAdd(&h2[2 * STS_NBIN + i], s_lo[i]);
+        }
+    }
+    if (!sts_last_block(&ctl->done[1], &s_flag)) return;
+    if (threadIdx.x == 0) {
+        s_sub.cnt_before = ctl->cnt_before;
+        s_sub.mb = 0;
+        s_sub.vpre = 0;
+        s_sub.vshift = 116;
+        s_sub.count = ctl->sub_count;
+    }
+    __syncthreads();
+    const u128 R = make128(ctl->R_lo, ctl->R_hi);
+    if (pick_digit<256>(h2, h2 + STS_NBIN, h2 + 2 * STS_NBIN, true, ctl->K, R, 11, &s_sub, s_m, s_c, &s_hit)) {
+        if (threadIdx.x == 0) {
+            sub_store(s_sub, ctl);
+            ctl->level = 2;
+        }
+    } else if (threadIdx.x == 0) {
+        atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+    }
+    for (int i = threadIdx.x; i < 3 * STS_NBIN; i += 256) st_agent(&h2[i], 0ull);
+}
+
+// ---------------------------------------------------------------------------
+// final levels and the exact cut, one workgroup of 1024 threads
+// ---------------------------------------------------------------------------
+constexpr int FT = 1024;
+
+__global__ void __launch_bounds__(FT) k_final(PassBufs b)
+{
+    // LDS: the level histograms and the sort buffer share one region
+    __shared__ __attribute__((aligned(16))) unsigned char s_raw[STS_SMALL * sizeof(u128)];
+    __shared__ u128 s_m[FT];
+    __shared__ u64 s_c[FT];
+    __shared__ u32 s_hit, s_n;
+    u64 *h_cnt = reinterpret_cast<u64 *>(s_raw);
+    u64 *h_hi = h_cnt + STS_NBIN;
+    u64 *h_lo = h_hi + STS_NBIN;
+    u128 *sv = reinterpret_cast<u128 *>(s_raw);
+    static_assert(3 * STS_NBIN * sizeof(u64) <= STS_SMALL * sizeof(u128), "LDS union");
+
+    __shared__ Sub s_sub;
+    DevCtl *ctl = b.ctl;
+    if (ctl->keep_all) return;
+    if (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW)) return;
+    const int t = threadIdx.x;
+    const int e = ctl->e_star;
+    const u64 n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
+    const u64 K = ctl->K;
+    const u128 R = make128(ctl->R_lo, ctl->R_hi);
+    if (t == 0) sub_load(s_sub, ctl);
+    __syncthreads();
+
+    // further levels until the subset fits the LDS sort
+    while (s_sub.count > STS_SMALL && s_sub.vshift > 0) {
+        const int vshift = s_sub.vshift;
+        const int dw = vshift < 11 ? vshift : 11;
+        const u128 vpre = s_sub.vpre;
+        for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
+        __syncthreads();
+        for (u64 i = t; i < n; i += FT) {
+            const u128 v = rank_key(b.side_w[i], b.side_key[i]);
+            if ((v >> vshift) != vpre) continue;
+            const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
+            const u64 mant = mant_of_v(v, e);
+            atomicAdd((unsigned long long *)&h_cnt[d], 1ull);
+            atomicAdd((unsigned long long *)&h_hi[d], mant >> 26);
+            atomicAdd((unsigned long long *)&h_lo[d], mant & ((1ull << 26) - 1));
+        }
+        __syncthreads();
+        if (!pick_digit<FT>(h_cnt, h_hi, h_lo, false, K, R, dw, &s_sub, s_m, s_c, &s_hit)) {
+            if (t == 0) atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+            return;
+        }
+    }
+
+    // gather the subset and sort it by V
+    const int vshift = s_sub.vshift;
+    const u128 vpre = s_sub.vpre;
+    if (t == 0) s_n = 0;
+    __syncthreads();
+    for (u64 i = t; i < n; i += FT) {
+        const u128 v = rank_key(b.side_w[i], b.side_key[i]);
+        if ((v >> vshift) != vpre) continue;
+        const u32 slot = atomicAdd(&s_n, 1u);
+        if (slot < STS_SMALL) sv[slot] = v;
+    }
+    __syncthreads();
+    const u32 m = s_n;
+    if (m == 0 || m > STS_SMALL) {
+        if (t == 0) atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+        return;
+    }
+    u32 P = 1;
+    while (P < m) P <<= 1;
+    for (u32 i = m + t; i < P; i += FT) sv[i] = ~(u128)0;
+    __syncthreads();
+    for (u32 k = 2; k <= P; k <<= 1) {
+        for (u32 j = k >> 1; j > 0; j >>= 1) {
+            for (u32 i = t; i < P; i += FT) {
+                const u32 ixj = i ^ j;
+                if (ixj > i) {
+                    const u128 a = sv[i], c = sv[ixj];
+                    const bool up = (i & k) == 0;
+                    if ((a > c) == up) {
+                        sv[i] = c;
+                        sv[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // exact prefix in rank order: thread t owns elements 4t .. 4t+3
+    constexpr int PER = STS_SMALL / FT;
+    u128 loc[PER];
+    u128 acc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const u32 r = PER * t + k;
+        if (r < m) acc += (u128)mant_of_v(sv[r], e);
+        loc[k] = acc;
+    }
+    s_m[t] = acc;
+    if (t == 0) s_hit = 0xffffffffu;
+    __syncthreads();
+    u128 inc = acc;
+    for (int d = 1; d < FT; d <<= 1) {
+        u128 o = 0;
+        if (t >= d) o = s_m[t - d];
+        __syncthreads();
+        if (t >= d) {
+            inc += o;
+            s_m[t] = inc;
+        }
+        __syncthreads();
+    }
+    const u128 excl = inc - acc;
+    const u64 cb = s_sub.cnt_before;
+    const u128 mb = s_sub.mb;
+    u32 hit = 0xffffffffu;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const u32 r = PER * t + k;
+        if (hit == 0xffffffffu && r < m) {
+            const bool hk = K > 0 && cb + r + 1 >= K;
+            const bool hp = mb + excl + loc[k] >= R;
+            if (hk || hp) hit = r;
+        }
+    }
+    if (hit != 0xffffffffu) atomicMin(&s_hit, hit);
+    __syncthreads();
+    const u32 first = s_hit;
+    if (first == 0xffffffffu) {
+        if (t == 0) atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+        return;
+    }
+    if (hit == first) {
+        const int k = (int)first - PER * t;
+        const u128 v = sv[first];
+        const u64 frac = ((1ull << 52) - 1) - (u64)(v >> 64);
+        const u128 mk = mb + excl + loc[k];
+        Big S = ctl->S_excl;
+        big_add_shifted(S, (u64)mk, (u64)(mk >> 64), unit_bit(e));
+        const double Sd = big_to_double(S);
+        const u64 L = cb + first + 1;
+        const int dropped = L < ctl->n_cand;
+        ctl->L = L;
+        ctl->thr_wbits = ((u64)e << 52) | frac;
+        ctl->thr_key = (u64)v;
+        ctl->dropped = dropped;
+        ctl->S = Sd;
+        ctl->scale = dropped ? 1.0 / sqrt(Sd) : 1.0;
+        ctl->frac = Sd / ctl->W;
+        if (dropped) ctl->log10_cum += log10(ctl->frac);
+    }
+}
+
+__global__ void k_init_state(u64 *keys, double2 *amps64, float2 *amps32, u64 *n_out)
+{
+    keys[0] = 0;
+    if (amps64) amps64[0] = make_double2(1.0, 0.0);
+    if (amps32) amps32[0] = make_float2(1.0f, 0.0f);
+    *n_out = 1;
+}
+
+__global__ void k_set_n(u64 *n_out, u64 n) { *n_out = n; }
+
+} // namespace
+
+hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pick1, dim3(1), dim3(256), 0, s, b, groups, peak_only);
+    return hipGetLastError();
+}
+
+hipError_t launch_side_hist(const PassBufs &b, u64 *h2, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_side_hist, dim3(grid), dim3(256), 0, s, b, h2);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const PassBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(FT), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, keys, prec == 0 ? (double2 *)amps : nullptr,
+                       prec == 0 ? nullptr : (float2 *)amps, n_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_n, dim3(1), dim3(1), 0, s, n_out, n);
+    return hipGetLastError();
+}

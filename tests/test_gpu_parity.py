@@ -1,0 +1,267 @@
+"""HIP path against the CPU oracle, element by element (needs the GPU).
+
+FP64 (c128): key sets must match exactly and amplitudes within 1e-12 (the
+kernels follow the oracle's operation order, so they are expected to agree
+bit for bit; the tolerance is the contract). c64: same peak, per-step kept
+fraction within 1e-6, per-term error within 1e-5 on the common keys.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import c_oracle as CO
+from oracle import dense as D
+from oracle import dict_oracle as O
+from paper_2607_07816_amd import circuits as C
+from tests.helpers import arrays_to_dict, random_state
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2607_07816_amd import _lib
+    return _lib
+
+
+def gpu_step(S, keys, amps, n, qubits, U, K, p, prec="c128", cap=None, truncate=True):
+    m = len(qubits)
+    cap = cap or max((len(keys) << m) + 16, 1024)
+    with S.State(n, K=K, p=p, precision=prec, capacity=cap) as st:
+        st.load_terms(keys, amps)
+        st.apply_gate(qubits, U)
+        if truncate:
+            st.truncate()
+        k, a = st.read_terms()
+        stats = st.stats() if truncate else None
+    return k, a, stats
+
+
+def oracle_step(keys, amps, qubits, U, K, p, truncate=True):
+    k, a, info = CO.step(keys, amps, qubits, U, K, p, truncate)
+    k, a = CO.sorted_terms(k, a)
+    return k, a, info
+
+
+def assert_same_fp64(kg, ag, ko, ao):
+    assert kg.shape == ko.shape, (kg.shape, ko.shape)
+    assert np.array_equal(kg, ko)
+    err = np.abs(ag - ao).max() if len(ag) else 0.0
+    assert err <= TOL64, err
+
+
+# ---------------------------------------------------------------------------
+# gate application, no truncation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
+def test_apply_matches_oracle(S, m):
+    rng = np.random.default_rng(10 + m)
+    for n, nterms in ((12, 300), (30, 5000), (64, 9000)):
+        say(f"apply m={m} n={n} N={nterms}")
+        keys, amps = random_state(rng, n, nterms)
+        if n == 64:  # exercise the top key bit
+            keys = keys | np.uint64(1 << 63) * (np.arange(len(keys)) % 2).astype(np.uint64)
+            keys, idx = np.unique(keys, return_index=True)
+            amps = amps[idx]
+        qs = tuple(int(q) for q in rng.choice(n, size=m, replace=False))
+        U = C.haar_unitary(rng, 1 << m)
+        kg, ag, _ = gpu_step(S, keys, amps, n, qs, U, 0, 0.0, truncate=False)
+        ko, ao, _ = oracle_step(keys, amps, qs, U, 0, 0.0, truncate=False)
+        assert_same_fp64(kg, ag, ko, ao)
+        assert np.array_equal(ag.view(np.uint64), ao.view(np.uint64))  # bitwise
+
+
+def test_permutations_keep_terms_and_bits(S):
+    rng = np.random.default_rng(3)
+    keys, amps = random_state(rng, 20, 7000)
+    for g, m in ((C.X_GATE, 1), (C.CNOT_GATE, 2), (C.SWAP_GATE, 2), (C.TOFFOLI_GATE, 3)):
+        qs = tuple(int(q) for q in rng.choice(20, size=m, replace=False))
+        say(f"perm m={m} qs={qs}")
+        kg, ag, _ = gpu_step(S, keys, amps, 20, qs, g, 0, 0.0, truncate=False)
+        ko, ao, _ = oracle_step(keys, amps, qs, g, 0, 0.0, truncate=False)
+        assert kg.shape[0] == keys.shape[0]
+        assert_same_fp64(kg, ag, ko, ao)
+        assert np.array_equal(ag.view(np.uint64), ao.view(np.uint64))
+
+
+# ---------------------------------------------------------------------------
+# one gate plus one truncation, several tiles and a ragged tail
+# ---------------------------------------------------------------------------
+CASES = [
+    # n, N, m, K, p
+    (16, 3000, 2, 1000, 0.0),
+    (24, 10007, 2, 4096, 0.0),
+    (24, 10007, 2, 0, 0.9),
+    (24, 10007, 2, 30000, 0.99),
+    (24, 10007, 2, 5000, 0.999),
+    (40, 20011, 1, 8000, 0.0),
+    (40, 20011, 3, 50000, 0.95),
+    (48, 6000, 4, 7000, 0.0),
+    (48, 4000, 5, 0, 0.5),
+    (20, 1500, 2, 10 ** 6, 0.0),   # K above the candidate count: no-op
+    (20, 1500, 2, 1, 0.0),         # K = 1
+]
+
+
+@pytest.mark.parametrize("n,N,m,K,p", CASES)
+def test_step_fp64(S, n, N, m, K, p):
+    rng = np.random.default_rng(n * 1000 + N + m)
+    keys, amps = random_state(rng, n, N)
+    qs = tuple(int(q) for q in rng.choice(n, size=m, replace=False))
+    U = C.haar_unitary(rng, 1 << m)
+    say(f"step fp64 n={n} N={N} m={m} K={K} p={p}")
+    kg, ag, st = gpu_step(S, keys, amps, n, qs, U, K, p)
+    ko, ao, info = oracle_step(keys, amps, qs, U, K, p)
+    assert_same_fp64(kg, ag, ko, ao)
+    assert np.array_equal(ag.view(np.uint64), ao.view(np.uint64))
+    assert st["candidates"] == CO.apply(keys, amps, qs, U)[0].shape[0]
+    if info is not None:
+        assert st["W"] == info["W"]
+        assert st["kept_fraction"] == info["fraction"]
+
+
+def test_ties_keep_smallest_keys(S):
+    # H on every qubit: 2^n bitwise-equal weights; top-K keeps the K smallest keys
+    n = 12
+    keys = np.zeros(1, dtype=np.uint64)
+    amps = np.ones(1, dtype=np.complex128)
+    for K in (1, 37, 1000, 4095, 4096):
+        with S.State(n, K=K, precision="c128", capacity=1 << 14) as st:
+            st.load_terms(keys, amps)
+            for q in range(n):
+                st.apply_gate((q,), C.H_GATE)
+                if q == n - 1:
+                    st.truncate()
+            kg, ag = st.read_terms()
+        say(f"ties K={K}")
+        assert np.array_equal(kg, np.arange(K, dtype=np.uint64))
+
+
+def test_pmass_exact_boundary(S):
+    # 40 equal weights: the p = 0.5 cut reaches the target exactly at 20 terms
+    keys = np.arange(40, dtype=np.uint64) * np.uint64(3)
+    amps = np.full(40, 0.125, dtype=np.complex128)
+    for p, L in ((0.5, 20), (0.25, 10), (0.75, 30)):
+        with S.State(10, K=0, p=p, precision="c128", capacity=1024) as st:
+            st.load_terms(keys, amps)
+            st.truncate()
+            kg, _ = st.read_terms()
+        assert np.array_equal(kg, keys[:L])
+
+
+def test_truncate_without_gate_and_empty_state(S):
+    rng = np.random.default_rng(5)
+    keys, amps = random_state(rng, 30, 5000, normalise=False)
+    with S.State(30, K=1234, p=0.8, precision="c128", capacity=1 << 14) as st:
+        st.load_terms(keys, amps)
+        st.truncate()
+        kg, ag = st.read_terms()
+    ko, ao, info = CO.truncate(keys, amps, 1234, 0.8)
+    ko, ao = CO.sorted_terms(ko, ao)
+    assert_same_fp64(kg, ag, ko, ao)
+    with S.State(30, K=10, precision="c128", capacity=1024) as st:
+        st.load_terms(np.zeros(0, np.uint64), np.zeros(0, np.complex128))
+        st.apply_gate((3, 7), C.haar_su(rng, 4))
+        st.truncate()
+        assert st.num_terms() == 0
+
+
+# ---------------------------------------------------------------------------
+# whole circuits
+# ---------------------------------------------------------------------------
+def test_small_workload_end_to_end(S):
+    from paper_2607_07816_amd.run import run_circuit
+    c, cfg = C.workload_small()
+    say("e2e peaked10")
+    st = run_circuit(c, K=cfg["K"], p=cfg["p"], precision="c128", capacity=4096)
+    kg, ag = st.read_terms()
+    key, prob = st.peak()
+    st.close()
+    ref = O.run_circuit(c.gates, c.truncate_after, cfg["K"], cfg["p"])
+    ko = np.array(sorted(ref), dtype=np.uint64)
+    ao = np.array([complex(*ref[int(k)]) for k in ko])
+    assert_same_fp64(kg, ag, ko, ao)
+    psi = D.run_dense(c.n, c.gates)
+    assert np.abs(psi[kg.astype(np.int64)] - ag).max() <= 1e-12
+    assert key == c.hidden == O.peak(ref)[0]
+    assert abs(prob - O.peak(ref)[1]) <= 1e-15
+
+
+def test_truncated_circuit_fp64_exact(S):
+    from paper_2607_07816_amd.run import run_circuit
+    c = C.peaked_circuit(20, 6, 0.03, 77, pairs="random", u3_layers=False)
+    for K, p in ((512, 0.0), (0, 0.9), (4096, 0.999)):
+        say(f"e2e n20 K={K} p={p}")
+        st = run_circuit(c, K=K, p=p, precision="c128", capacity=1 << 16)
+        kg, ag = st.read_terms()
+        key, _ = st.peak()
+        st.close()
+        ko, ao = CO.run_circuit(c.gates, c.truncate_after, K, p)
+        ko, ao = CO.sorted_terms(ko, ao)
+        assert_same_fp64(kg, ag, ko, ao)
+        assert key == CO.peak(ko, ao)[0] == c.hidden
+
+
+def test_c64_step_tolerances(S):
+    rng = np.random.default_rng(21)
+    for n, N, m, K, p in ((24, 20000, 2, 8192, 0.0), (36, 30000, 2, 0, 0.99), (48, 15000, 1, 5000, 0.99)):
+        keys, amps = random_state(rng, n, N)
+        amps = amps.astype(np.complex64).astype(np.complex128)  # the same input on both sides
+        qs = tuple(int(q) for q in rng.choice(n, size=m, replace=False))
+        U = C.haar_su(rng, 1 << m)
+        say(f"c64 step n={n} N={N} K={K} p={p}")
+        kg, ag, st = gpu_step(S, keys, amps, n, qs, U, K, p, prec="c64")
+        ko, ao, info = oracle_step(keys, amps, qs, U, K, p)
+        assert abs(st["kept_fraction"] - info["fraction"]) <= 1e-6
+        common, ig, io = np.intersect1d(kg, ko, return_indices=True)
+        assert len(common) >= 0.99 * len(ko)
+        assert np.abs(ag[ig] - ao[io]).max() <= 1e-5
+        assert kg[np.argmax(np.abs(ag))] == ko[np.argmax(np.abs(ao))]
+
+
+def test_c64_circuit_same_peak(S):
+    from paper_2607_07816_amd.run import run_circuit
+    c = C.peaked_circuit(24, 6, 0.02, 5, pairs="random", u3_layers=False)
+    say("c64 e2e n24")
+    st = run_circuit(c, K=4096, p=0.0, precision="c64", capacity=1 << 16)
+    key, prob = st.peak()
+    s = st.stats()
+    st.close()
+    ko, ao = CO.run_circuit(c.gates, c.truncate_after, 4096, 0.0)
+    assert key == CO.peak(ko, ao)[0] == c.hidden
+    assert abs(prob - CO.peak(ko, ao)[1]) <= 1e-5
+
+
+def test_determinism(S):
+    from paper_2607_07816_amd.run import run_circuit
+    c = C.peaked_circuit(30, 5, 0.03, 8, pairs="random", u3_layers=False)
+    outs = []
+    for _ in range(2):
+        st = run_circuit(c, K=20000, p=0.99, precision="c64", capacity=1 << 17)
+        outs.append(st.read_terms())
+        st.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
+
+
+def test_argument_errors(S):
+    with S.State(8, K=16, precision="c128", capacity=1024) as st:
+        with pytest.raises(S.StsError):
+            st.apply_gate((1, 1), np.eye(4))
+        with pytest.raises(S.StsError):
+            st.apply_gate((8,), np.eye(2))
+        with pytest.raises(S.StsError):
+            st.load_terms(np.array([1, 1], np.uint64), np.ones(2, np.complex128))
+        with pytest.raises(S.StsError):
+            st.load_terms(np.array([256], np.uint64), np.ones(1, np.complex128))
+        # nothing changed
+        assert st.num_terms() == 1
+        assert st.peak() == (0, 1.0)
