@@ -152,7 +152,8 @@ typedef enum {
     STS_K_SIDE_HIST = 6,    /* mantissa-level cut                            */
     STS_K_FINAL = 7,        /* last levels and LDS sort                      */
     STS_K_GROUP_EMIT = 8,   /* gate + survivor write                         */
-    STS_K_COUNT = 9
+    STS_K_SIDE_EXTRACT = 9, /* copy of the mantissa-level subset             */
+    STS_K_COUNT = 10
 } sts_kernel_kind;
 
 /* Turn per-kernel timing on (1) or off (0). While on, every kernel launch is

@@ -36,7 +36,8 @@ u64 align_up(u64 x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
-    u64 ctl, keys[3], amps[3], side_key, side_w, h1, h2, best, rhist, roffs, look_radix, look_comp, tctr, dU, total;
+    u64 ctl, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rhist, roffs, look_radix, look_comp,
+        tctr, dU, total;
 };
 
 Layout make_layout(u64 cap, int prec)
@@ -57,6 +58,8 @@ Layout make_layout(u64 cap, int prec)
     for (int i = 0; i < 3; ++i) L.amps[i] = take(cap * asz);
     L.side_key = take(scap * 8);
     L.side_w = take(scap * 8);
+    L.sub_key = take((u64)STS_SUB_CAP * 8);
+    L.sub_w = take((u64)STS_SUB_CAP * 8);
     L.h1 = take(3 * STS_NBIN * 8);
     L.h2 = take(3 * STS_NBIN * 8);
     L.best = take(2 * STS_MAX_GROUPS * 8);
@@ -89,7 +92,7 @@ struct sts_ctx {
     u64 n_bound = 1;        // upper bound on the terms in buffer cur
     DevCtl *ctl = nullptr;
     u64 *h1 = nullptr, *h2 = nullptr, *best = nullptr;
-    u64 *side_key = nullptr, *side_w = nullptr;
+    u64 *side_key = nullptr, *side_w = nullptr, *sub_key = nullptr, *sub_w = nullptr;
     u64 *rhist = nullptr, *roffs = nullptr, *look_radix = nullptr, *look_comp = nullptr;
     u32 *tctr = nullptr;
     double *dU = nullptr;
@@ -201,6 +204,9 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     b.side_key = c->side_key;
     b.side_w = c->side_w;
     b.side_cap = c->scap;
+    b.sub_key = c->sub_key;
+    b.sub_w = c->sub_w;
+    b.sub_cap = STS_SUB_CAP;
     if (out >= 0) {
         b.out_keys = c->keys[out];
         b.out_amps = c->amps[out];
@@ -395,6 +401,8 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     }
     c->side_key = (u64 *)(c->mem + L.side_key);
     c->side_w = (u64 *)(c->mem + L.side_w);
+    c->sub_key = (u64 *)(c->mem + L.sub_key);
+    c->sub_w = (u64 *)(c->mem + L.sub_w);
     c->h1 = (u64 *)(c->mem + L.h1);
     c->h2 = (u64 *)(c->mem + L.h2);
     c->best = (u64 *)(c->mem + L.best);
@@ -498,6 +506,7 @@ sts_status sts_truncate(sts_ctx *c)
     STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_compact(c->prec, STS_KIND_EXTRACT, c->gate, b, tiles, c->stream));
     const int sg = (int)std::min<u64>(std::max<u64>(ceil_div(std::min(cb, c->scap), 256), 1), STS_SIDE_GROUPS);
     STS_LAUNCH(c, STS_K_SIDE_HIST, launch_side_hist(b, c->h2, sg, c->stream));
+    STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, sg, c->stream));
     STS_LAUNCH(c, STS_K_FINAL, launch_final(b, c->stream));
     u64 nb = c->K ? std::min<u64>(c->K, cb) : cb;
     if (nb > c->cap) {

@@ -38,6 +38,7 @@ struct DevCtl {
     u64 tot_updates;     // input terms of those truncations
     u64 tot_cand;        // candidates of those truncations
     u64 side_n;          // candidates copied to the side buffer
+    u64 sub_n;           // side-buffer terms copied to the level-2 subset buffer
     u32 done[4];         // last-workgroup counters, one per kernel kind
     u32 flags;           // STS_F_* below
     u32 pad0;

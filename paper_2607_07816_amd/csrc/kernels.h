@@ -35,6 +35,9 @@ struct PassBufs {
     u64 *side_key;        // side buffer: candidates of the exponent holding the cut
     u64 *side_w;
     u64 side_cap;
+    u64 *sub_key;         // the level-2 subset of the side buffer
+    u64 *sub_w;
+    u64 sub_cap;
     u64 *out_keys;        // new state
     void *out_amps;
     u64 out_cap;
@@ -57,6 +60,7 @@ hipError_t launch_group_compact(int prec, int kind, const GateArg &g, const Pass
                                 hipStream_t s);
 hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, hipStream_t s);
 hipError_t launch_side_hist(const PassBufs &b, u64 *h2, int grid, hipStream_t s);
+hipError_t launch_side_extract(const PassBufs &b, int grid, hipStream_t s);
 hipError_t launch_final(const PassBufs &b, hipStream_t s);
 hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s);
 hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s);
@@ -67,3 +71,4 @@ hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s);
 #define STS_GTILE (STS_WG * STS_GROUP_ITEMS)     // elements per compaction tile
 #define STS_MAX_GROUPS 1024                      // persistent grid of the histogram pass
 #define STS_SIDE_GROUPS 512
+#define STS_SUB_CAP (1u << 16)                   // level-2 subset buffer (terms)

@@ -409,11 +409,48 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
         if (threadIdx.x == 0) {
             sub_store(s_sub, ctl);
             ctl->level = 2;
+            ctl->sub_n = 0;
         }
     } else if (threadIdx.x == 0) {
         atomicOr(&ctl->flags, STS_F_UNRESOLVED);
     }
     for (int i = threadIdx.x; i < 3 * STS_NBIN; i += 256) st_agent(&h2[i], 0ull);
+}
+
+// ---------------------------------------------------------------------------
+// copy the level-2 subset out of the side buffer (many workgroups), so the
+// final workgroup reads a few thousand terms instead of the whole buffer
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
+{
+    DevCtl *ctl = b.ctl;
+    if (ctl->keep_all || (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
+    if (ctl->sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
+    const u64 n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
+    const int vshift = ctl->vshift;
+    const u128 vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
+    const u64 lt = sts_lanemask_lt();
+    const u64 stride = (u64)gridDim.x * 256;
+    for (u64 base = (u64)blockIdx.x * 256; base < n; base += stride) {
+        const u64 i = base + threadIdx.x;
+        bool take = false;
+        u64 w = 0, k = 0;
+        if (i < n) {
+            w = b.side_w[i];
+            k = b.side_key[i];
+            take = (rank_key(w, k) >> vshift) == vpre;
+        }
+        const u64 mask = __ballot(take);
+        if (!mask) continue;
+        const int leader = __ffsll((long long)mask) - 1;
+        u64 pos = 0;
+        if (sts_lane() == leader) pos = atomicAdd((unsigned long long *)&ctl->sub_n, (u64)__popcll(mask));
+        pos = __shfl(pos, leader, 64) + (u64)__popcll(mask & lt);
+        if (take && pos < b.sub_cap) {
+            b.sub_key[pos] = k;
+            b.sub_w[pos] = w;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -440,7 +477,11 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     if (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW)) return;
     const int t = threadIdx.x;
     const int e = ctl->e_star;
-    const u64 n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
+    // the level-2 subset buffer when it holds the subset, else the side buffer
+    const bool small = ctl->sub_count <= b.sub_cap;
+    const u64 *src_w = small ? b.sub_w : b.side_w;
+    const u64 *src_k = small ? b.sub_key : b.side_key;
+    const u64 n = small ? ctl->sub_n : (ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap);
     const u64 K = ctl->K;
     const u128 R = make128(ctl->R_lo, ctl->R_hi);
     if (t == 0) sub_load(s_sub, ctl);
@@ -454,7 +495,7 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
         __syncthreads();
         for (u64 i = t; i < n; i += FT) {
-            const u128 v = rank_key(b.side_w[i], b.side_key[i]);
+            const u128 v = rank_key(src_w[i], src_k[i]);
             if ((v >> vshift) != vpre) continue;
             const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
             const u64 mant = mant_of_v(v, e);
@@ -475,7 +516,7 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     if (t == 0) s_n = 0;
     __syncthreads();
     for (u64 i = t; i < n; i += FT) {
-        const u128 v = rank_key(b.side_w[i], b.side_key[i]);
+        const u128 v = rank_key(src_w[i], src_k[i]);
         if ((v >> vshift) != vpre) continue;
         const u32 slot = atomicAdd(&s_n, 1u);
         if (slot < STS_SMALL) sv[slot] = v;
@@ -593,6 +634,12 @@ hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, hipStream_
 hipError_t launch_side_hist(const PassBufs &b, u64 *h2, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_side_hist, dim3(grid), dim3(256), 0, s, b, h2);
+    return hipGetLastError();
+}
+
+hipError_t launch_side_extract(const PassBufs &b, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_side_extract, dim3(grid), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
