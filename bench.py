@@ -45,6 +45,8 @@ def kernel_bytes(kind: str, amp_bytes: int, n_in: float, n_out: float, n_side: f
         return 8 * n_side
     if kind == "side_extract":
         return 16 * n_side
+    if kind == "tile_kept":
+        return 16 * n_side
     return 0.0
 
 

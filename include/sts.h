@@ -153,7 +153,9 @@ typedef enum {
     STS_K_FINAL = 7,        /* last levels and LDS sort                      */
     STS_K_GROUP_EMIT = 8,   /* gate + survivor write                         */
     STS_K_SIDE_EXTRACT = 9, /* copy of the mantissa-level subset             */
-    STS_K_COUNT = 10
+    STS_K_TILE_KEPT = 10,   /* survivors per tile                            */
+    STS_K_TILE_SCAN = 11,   /* output offsets per tile                       */
+    STS_K_COUNT = 12
 } sts_kernel_kind;
 
 /* Turn per-kernel timing on (1) or off (0). While on, every kernel launch is

@@ -27,7 +27,7 @@ EXPORTS = (
 )
 
 KERNEL_KINDS = ("radix_hist", "radix_scan", "radix_pass", "group_hist", "pick1", "group_extract",
-                "side_hist", "final", "group_emit", "side_extract")
+                "side_hist", "final", "group_emit", "side_extract", "tile_kept", "tile_scan")
 
 
 class StsError(RuntimeError):

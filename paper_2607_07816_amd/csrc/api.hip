@@ -37,13 +37,19 @@ u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
     u64 ctl, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rhist, roffs, look_radix, look_comp,
-        tctr, dU, total;
+        t_above, t_side, t_off, tctr, dU, total;
 };
+
+// tiles of the LDS-tiled passes (2048 terms each) and the side-buffer entries:
+// one slab of 2048 << m entries per tile, m <= 3
+u64 tiled_tiles(u64 cap) { return (cap + 2047) / 2048 + 1; }
+u64 side_capacity(u64 cap) { return tiled_tiles(cap) * (2048ull << 3); }
 
 Layout make_layout(u64 cap, int prec)
 {
     const u64 asz = prec == STS_C128 ? 16 : 8;
-    const u64 scap = 4 * cap;
+    const u64 scap = side_capacity(cap);
+    const u64 ttiles = tiled_tiles(cap);
     const u64 tiles = ceil_div(cap, STS_TILE);
     const u64 gtiles = ceil_div(cap, STS_GTILE);
     Layout L;
@@ -67,6 +73,9 @@ Layout make_layout(u64 cap, int prec)
     L.roffs = take(STS_MAX_PASSES * 256 * 8);
     L.look_radix = take(STS_MAX_PASSES * tiles * 256 * 8);
     L.look_comp = take(gtiles * 8);
+    L.t_above = take(ttiles * 4);
+    L.t_side = take(ttiles * 4);
+    L.t_off = take(ttiles * 8);
     L.tctr = take(16 * 4);
     L.dU = take(kULen * 8);
     L.total = o;
@@ -94,6 +103,8 @@ struct sts_ctx {
     u64 *h1 = nullptr, *h2 = nullptr, *best = nullptr;
     u64 *side_key = nullptr, *side_w = nullptr, *sub_key = nullptr, *sub_w = nullptr;
     u64 *rhist = nullptr, *roffs = nullptr, *look_radix = nullptr, *look_comp = nullptr;
+    u32 *t_above = nullptr, *t_side = nullptr;
+    u64 *t_off = nullptr;
     u32 *tctr = nullptr;
     double *dU = nullptr;
     double *hU = nullptr;    // pinned staging of U for m >= 4
@@ -213,17 +224,23 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     }
     b.out_cap = c->cap;
     b.look = c->look_comp;
+    b.t_above = c->t_above;
+    b.t_side = c->t_side;
+    b.t_off = c->t_off;
     b.tile_ctr = c->tctr + 4;
     return b;
 }
 
-int hist_groups(u64 n_bound)
+// workgroups of the histogram pass (persistent; m <= 3 walks 2048-term tiles),
+// at most as many as are resident at once
+int hist_groups(int prec, u64 n_bound, int m)
 {
-    const u64 g = ceil_div(n_bound ? n_bound : 1, STS_WG);
-    return (int)std::min<u64>(std::max<u64>(g, 1), STS_MAX_GROUPS);
+    const u64 g = ceil_div(n_bound ? n_bound : 1, m <= 3 ? 2048 : STS_WG);
+    const u64 cap = (u64)std::min(group_hist_capacity(prec, m), STS_MAX_GROUPS);
+    return (int)std::min<u64>(std::max<u64>(g, 1), cap);
 }
 
-int compact_tiles(u64 n_bound) { return (int)std::max<u64>(ceil_div(n_bound, STS_GTILE), 1); }
+int compact_tiles(u64 n_bound, int m) { return (int)sts_compact_groups(n_bound, m); }
 
 // copy the control block to the host and wait; map device-side error flags
 sts_status sync_ctl(sts_ctx *c)
@@ -255,7 +272,7 @@ sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
     const int grid = (int)std::min<u64>(std::max<u64>(ceil_div(nb, STS_WG * 8), 1), 1024);
     STS_LAUNCH(c, STS_K_RADIX_HIST, launch_radix_hist(c->keys[c->cur], &c->ctl->cnt[c->cur], notmask, hb, npass, c->rhist, grid,
                                  c->stream));
-    STS_LAUNCH(c, STS_K_RADIX_SCAN, launch_radix_scan(c->rhist, c->roffs, npass, c->stream));
+    STS_LAUNCH(c, STS_K_RADIX_SCAN, launch_radix_scan(c->rhist, c->roffs, npass, &c->ctl->radix_epoch, c->stream));
     const int tiles = (int)std::max<u64>(ceil_div(nb, STS_TILE), 1);
     const int a = (c->cur + 1) % 3, b = (c->cur + 2) % 3;
     int src = c->cur, dst = a;
@@ -263,8 +280,8 @@ sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
         const int shift = 64 - hb + 8 * p;
         STS_LAUNCH(c, STS_K_RADIX_PASS, launch_radix_pass(c->prec, c->keys[src], c->amps[src], c->keys[dst], c->amps[dst],
                                      &c->ctl->cnt[src], &c->ctl->cnt[dst], notmask, shift, c->roffs + 256 * p,
-                                     c->look_radix + (u64)p * c->tiles_cap * 256, c->tctr + p, next_epoch(c),
-                                     tiles, c->stream));
+                                     c->look_radix + (u64)p * c->tiles_cap * 256, c->tctr + p,
+                                     &c->ctl->radix_epoch, p, tiles, c->stream));
         src = dst;
         dst = dst == a ? b : a;
     }
@@ -277,9 +294,9 @@ sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
 sts_status count_candidates(sts_ctx *c, u64 *count)
 {
     PassBufs b = pass_bufs(c, c->cur, -1);
-    const int G = hist_groups(c->n_bound);
+    const int G = hist_groups(c->prec, c->n_bound, c->gate.m);
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, c->stream));
-    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, c->stream));
+    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, 0, c->stream));
     const sts_status st = sync_ctl(c);
     if (st != STS_OK) return st;
     *count = c->hctl->cand_all;
@@ -305,8 +322,17 @@ sts_status materialise(sts_ctx *c)
     const int dst = (c->cur + 1) % 3;
     PassBufs b = pass_bufs(c, c->cur, dst);
     b.materialise = 1;
-    b.epoch = next_epoch(c);
-    STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_compact(c->prec, STS_KIND_EMIT, c->gate, b, compact_tiles(c->n_bound), c->stream));
+    if (c->gate.m <= 3) {
+        const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
+        STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_TILE_KEPT, launch_tile_kept(b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_TILE_SCAN, launch_tile_scan(b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_emit_tiles(c->prec, c->gate, b, tt, c->stream));
+    } else {
+        b.epoch = next_epoch(c);
+        STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_compact(c->prec, STS_KIND_EMIT, c->gate, b,
+                                                             compact_tiles(c->n_bound, c->gate.m), c->stream));
+    }
     c->cur = dst;
     c->n_bound = std::min(bound, c->cap);
     c->pending = false;
@@ -378,7 +404,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     c->p = (mass > 0.0 && mass < 1.0) ? mass : 0.0;
     c->stream = (hipStream_t)hip_stream;
     c->cap = cap;
-    c->scap = 4 * cap;
+    c->scap = side_capacity(cap);
     c->tiles_cap = ceil_div(cap, STS_TILE);
     c->gtiles_cap = ceil_div(cap, STS_GTILE);
     const Layout L = make_layout(cap, precision);
@@ -410,6 +436,9 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     c->roffs = (u64 *)(c->mem + L.roffs);
     c->look_radix = (u64 *)(c->mem + L.look_radix);
     c->look_comp = (u64 *)(c->mem + L.look_comp);
+    c->t_above = (u32 *)(c->mem + L.t_above);
+    c->t_side = (u32 *)(c->mem + L.t_side);
+    c->t_off = (u64 *)(c->mem + L.t_off);
     c->tctr = (u32 *)(c->mem + L.tctr);
     c->dU = (double *)(c->mem + L.dU);
 
@@ -425,6 +454,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     c->hctl->p = c->p;
     c->hctl->scale = 1.0;
     c->hctl->frac = 1.0;
+    c->hctl->e_pred = -1;
     // zero the bookkeeping regions (everything but the term buffers)
     e = hipMemsetAsync(c->mem + L.h1, 0, L.total - L.h1, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->ctl, c->hctl, sizeof(DevCtl), hipMemcpyHostToDevice, c->stream);
@@ -466,6 +496,14 @@ sts_status sts_apply_gate(sts_ctx *c, int m, const int *qubits, const double *U)
         for (int i = 0; i < dim * dim; ++i) {
             g.ur[i] = U[2 * i];
             g.ui[i] = U[2 * i + 1];
+            g.fr[i] = (float)U[2 * i]; // nearest-even
+            g.fi[i] = (float)U[2 * i + 1];
+        }
+        for (int i = 0; i < dim; ++i) {
+            u64 d = 0;
+            for (int t = 0; t < m; ++t)
+                if ((i >> t) & 1) d |= 1ull << qubits[t];
+            g.dep[i] = d;
         }
     } else {
         // the previous copy from the staging buffer must have finished
@@ -498,12 +536,21 @@ sts_status sts_truncate(sts_ctx *c)
     const u64 cb = sat_shl(c->n_bound, c->gate.m);
     const int out = (c->cur + 1) % 3;
     PassBufs b = pass_bufs(c, c->cur, out);
-    const int G = hist_groups(c->n_bound);
-    const int tiles = compact_tiles(c->n_bound);
+    const int G = hist_groups(c->prec, c->n_bound, c->gate.m);
+    const int tiles = compact_tiles(c->n_bound, c->gate.m);
+    const bool tiled = c->gate.m <= 3;
+    b.predict = tiled ? 1 : 0; // the histogram pass also extracts the previous cut exponent
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, c->stream));
-    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, c->stream));
-    b.epoch = next_epoch(c);
-    STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_compact(c->prec, STS_KIND_EXTRACT, c->gate, b, tiles, c->stream));
+    b.predict = 0;
+    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, tiled ? 1 : 0, c->stream));
+    const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
+    if (tiled) {
+        STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
+    } else {
+        b.epoch = next_epoch(c);
+        STS_LAUNCH(c, STS_K_GROUP_EXTRACT,
+                   launch_group_compact(c->prec, STS_KIND_EXTRACT, c->gate, b, tiles, c->stream));
+    }
     const int sg = (int)std::min<u64>(std::max<u64>(ceil_div(std::min(cb, c->scap), 256), 1), STS_SIDE_GROUPS);
     STS_LAUNCH(c, STS_K_SIDE_HIST, launch_side_hist(b, c->h2, sg, c->stream));
     STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, sg, c->stream));
@@ -520,8 +567,14 @@ sts_status sts_truncate(sts_ctx *c)
         }
         nb = L;
     }
-    b.epoch = next_epoch(c);
-    STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_compact(c->prec, STS_KIND_EMIT, c->gate, b, tiles, c->stream));
+    if (tiled) {
+        STS_LAUNCH(c, STS_K_TILE_KEPT, launch_tile_kept(b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_TILE_SCAN, launch_tile_scan(b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_emit_tiles(c->prec, c->gate, b, tt, c->stream));
+    } else {
+        b.epoch = next_epoch(c);
+        STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_compact(c->prec, STS_KIND_EMIT, c->gate, b, tiles, c->stream));
+    }
     c->cur = out;
     c->n_bound = nb;
     c->pending = false;
@@ -537,9 +590,9 @@ sts_status sts_peak(sts_ctx *c, uint64_t *key, double *prob)
     if (st != STS_OK) return st;
     const GateArg g = identity_gate();
     PassBufs b = pass_bufs(c, c->cur, -1);
-    const int G = hist_groups(c->n_bound);
+    const int G = hist_groups(c->prec, c->n_bound, 0);
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, g, b, G, c->stream));
-    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, c->stream));
+    STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, 0, c->stream));
     st = sync_ctl(c);
     if (st != STS_OK) return st;
     if (c->hctl->cnt[c->cur] == 0) return STS_E_STATE;

@@ -37,11 +37,14 @@ struct DevCtl {
     u64 tot_steps;       // truncations run since init
     u64 tot_updates;     // input terms of those truncations
     u64 tot_cand;        // candidates of those truncations
-    u64 side_n;          // candidates copied to the side buffer
+    u64 side_n;          // candidates copied to the side buffer (dense layout)
+    u64 side_ntiles;     // tiled layout: tiles, each owning a slab of 2^side_slab_shift entries
+    int side_slab_shift;
+    int side_dense;      // 1: entries [0, side_n) (look-back pass); 0: per-tile slabs
     u64 sub_n;           // side-buffer terms copied to the level-2 subset buffer
     u32 done[4];         // last-workgroup counters, one per kernel kind
     u32 flags;           // STS_F_* below
-    u32 pad0;
+    u32 radix_epoch;     // look-back tag of the current sort's first pass (advanced on the device)
     // truncation rule
     u64 K;               // top-k (0 = off)
     double p;            // p-mass (off unless 0 < p < 1)
@@ -49,6 +52,8 @@ struct DevCtl {
     int keep_all;        // the rule keeps every candidate
     int dropped;         // L < C: rescale
     int e_star;          // exponent field of the level holding the L-th term
+    int e_pred;          // cut exponent of the previous truncation (-1: none)
+    int pred_hit;        // this truncation's cut exponent equals e_pred
     int level;           // last resolved level
     u64 cnt_before;      // terms ranked before the current subset
     u64 mb_lo, mb_hi;    // mantissa sum (units 2^(max(e*,1)-1075)) ranked before the subset inside e*
@@ -184,101 +189,124 @@ __device__ inline bool big_is_zero(const Big &a)
     return o == 0;
 }
 
+// a >>= 64 * k (whole limbs), with compile-time limb indices (a barrel of
+// conditional shifts), so nothing spills to scratch memory
+__device__ inline void big_shr_limbs(Big &a, int k)
+{
+#pragma unroll
+    for (int b = 16; b >= 1; b >>= 1) {
+        if (k & b) {
+#pragma unroll
+            for (int i = 0; i < STS_NL; ++i) a.l[i] = (i + b < STS_NL) ? a.l[i + b] : 0ull;
+        }
+    }
+}
+
+// any bit of a below bit position s set?
+__device__ inline bool big_any_below(const Big &a, int s)
+{
+    const int wl = s >> 6, wb = s & 63;
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i) {
+        if (i < wl) any |= a.l[i] != 0;
+        if (i == wl && wb) any |= (a.l[i] & ((1ull << wb) - 1)) != 0;
+    }
+    return any;
+}
+
+// a >>= s (truncating)
+__device__ inline void big_shr(Big &a, int s)
+{
+    big_shr_limbs(a, s >> 6);
+    const int wb = s & 63;
+    if (wb) {
+#pragma unroll
+        for (int i = 0; i < STS_NL; ++i) {
+            const u64 nxt = (i + 1 < STS_NL) ? a.l[i + 1] : 0ull;
+            a.l[i] = (a.l[i] >> wb) | (nxt << (64 - wb));
+        }
+    }
+}
+
 // r = ceil(a * m / 2^s)
 __device__ inline void big_mul_shr_ceil(Big &r, const Big &a, u64 m, int s)
 {
-    Big prod;
     u64 carry = 0;
+#pragma unroll
     for (int i = 0; i < STS_NL; ++i) {
         const u128 t = (u128)a.l[i] * m + carry;
-        prod.l[i] = (u64)t;
+        r.l[i] = (u64)t;
         carry = (u64)(t >> 64);
     }
-    const int wl = s >> 6, wb = s & 63;
-    bool any = false;
-    for (int i = 0; i < wl && i < STS_NL; ++i) any |= prod.l[i] != 0;
-    if (wl < STS_NL && wb) any |= (prod.l[wl] & ((1ull << wb) - 1)) != 0;
-    for (int i = 0; i < STS_NL; ++i) {
-        const int src = i + wl;
-        u64 v = 0;
-        if (src < STS_NL) {
-            v = prod.l[src] >> wb;
-            if (wb && src + 1 < STS_NL) v |= prod.l[src + 1] << (64 - wb);
-        }
-        r.l[i] = v;
-    }
+    const bool any = big_any_below(r, s);
+    big_shr(r, s);
     if (any) big_add_shifted(r, 1, 0, 0);
 }
 
 // ceil(a / 2^s) clamped to 2^128 - 1 (returned as lo, hi)
 __device__ inline void big_shr_ceil_u128(const Big &a, int s, u64 &lo, u64 &hi)
 {
-    const int wl = s >> 6, wb = s & 63;
-    bool any = false;
-    for (int i = 0; i < wl && i < STS_NL; ++i) any |= a.l[i] != 0;
-    if (wl < STS_NL && wb) any |= (a.l[wl] & ((1ull << wb) - 1)) != 0;
-    u64 w[3];
-    for (int k = 0; k < 3; ++k) {
-        const int src = wl + k;
-        u64 v = 0;
-        if (src < STS_NL) {
-            v = a.l[src] >> wb;
-            if (wb && src + 1 < STS_NL) v |= a.l[src + 1] << (64 - wb);
-        }
-        w[k] = v;
+    Big t = a;
+    const bool any = big_any_below(t, s);
+    big_shr(t, s);
+    bool over = false;
+#pragma unroll
+    for (int i = 2; i < STS_NL; ++i) over |= t.l[i] != 0;
+    if (over) {
+        lo = ~0ull;
+        hi = ~0ull;
+        return;
     }
-    bool big_hi = w[2] != 0;
-    for (int i = wl + 3; i < STS_NL; ++i) big_hi |= a.l[i] != 0;
-    if (big_hi) { lo = ~0ull; hi = ~0ull; return; }
-    lo = w[0];
-    hi = w[1];
+    lo = t.l[0];
+    hi = t.l[1];
     if (any) {
         lo += 1;
         if (lo == 0) {
             hi += 1;
-            if (hi == 0) { lo = ~0ull; hi = ~0ull; }
+            if (hi == 0) {
+                lo = ~0ull;
+                hi = ~0ull;
+            }
         }
     }
 }
 
-__device__ inline int big_top_bit(const Big &a)
-{
-    for (int i = STS_NL - 1; i >= 0; --i)
-        if (a.l[i]) return i * 64 + 63 - __clzll((long long)a.l[i]);
-    return -1;
-}
-
-__device__ inline int big_bit(const Big &a, int pos)
-{
-    if (pos < 0) return 0;
-    return (int)((a.l[pos >> 6] >> (pos & 63)) & 1);
-}
-
-__device__ inline bool big_any_below(const Big &a, int pos)
-{
-    if (pos <= 0) return false;
-    const int wl = pos >> 6, wb = pos & 63;
-    for (int i = 0; i < wl; ++i)
-        if (a.l[i]) return true;
-    return wb && (a.l[wl] & ((1ull << wb) - 1));
-}
-
-// nearest binary64 (ties to even)
+// nearest binary64 to a (ties to even), from the top 128 bits and a sticky bit
 __device__ inline double big_to_double(const Big &a)
 {
-    const int h = big_top_bit(a);
-    if (h < 0) return 0.0;
-    if (h < 53) return ldexp((double)a.l[0], -1074);
-    int lo = h - 52;
-    u64 mant = 0;
-    for (int b = h; b >= lo; --b) mant = (mant << 1) | (u64)big_bit(a, b);
-    const int guard = big_bit(a, lo - 1);
-    const bool sticky = big_any_below(a, lo - 1);
-    if (guard && (sticky || (mant & 1))) {
-        mant += 1;
-        if (mant == (1ull << 53)) { mant >>= 1; lo += 1; }
+    int top = -1;
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i)
+        if (a.l[i]) top = i;
+    if (top < 0) return 0.0;
+    u64 L0 = 0, L1 = 0, L2 = 0;
+    bool below = false;
+#pragma unroll
+    for (int i = 0; i < STS_NL; ++i) {
+        if (i == top) L0 = a.l[i];
+        if (i == top - 1) L1 = a.l[i];
+        if (i == top - 2) L2 = a.l[i];
+        if (i < top - 2) below |= a.l[i] != 0;
     }
-    return ldexp((double)mant, lo - 1074);
+    const int lz = __clzll((long long)L0);
+    const int h = top * 64 + 63 - lz; // position of the top set bit
+    if (h < 53) return ldexp((double)L0, -1074);
+    const u64 hi = lz ? (L0 << lz) | (L1 >> (64 - lz)) : L0; // bit 63 = bit h
+    const u64 lo = lz ? (L1 << lz) | (L2 >> (64 - lz)) : L1;
+    const bool rest = below || (lz ? (L2 << lz) != 0 : L2 != 0);
+    u64 mant = hi >> 11;
+    const bool guard = (hi >> 10) & 1ull;
+    const bool sticky = (hi & 0x3ffull) != 0 || lo != 0 || rest;
+    int lsb = h - 52;
+    if (guard && (sticky || (mant & 1ull))) {
+        mant += 1;
+        if (mant == (1ull << 53)) {
+            mant >>= 1;
+            lsb += 1;
+        }
+    }
+    return ldexp((double)mant, lsb - 1074);
 }
 
 // --------------------------------------------------------------------------

@@ -22,3 +22,12 @@ hipError_t group_c128_large_compact(int kind, const GateArg &g, const PassBufs &
     }
     return hipErrorInvalidValue;
 }
+
+int group_c128_large_hist_capacity(int m)
+{
+    switch (m) {
+    case 4: return hist_capacity<double2, 4>();
+    case 5: return hist_capacity<double2, 5>();
+    }
+    return 1;
+}

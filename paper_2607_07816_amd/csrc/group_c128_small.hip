@@ -26,3 +26,36 @@ hipError_t group_c128_small_compact(int kind, const GateArg &g, const PassBufs &
     }
     return hipErrorInvalidValue;
 }
+
+int group_c128_small_hist_capacity(int m)
+{
+    switch (m) {
+    case 0: return hist_capacity<double2, 0>();
+    case 1: return hist_capacity<double2, 1>();
+    case 2: return hist_capacity<double2, 2>();
+    case 3: return hist_capacity<double2, 3>();
+    }
+    return 1;
+}
+
+hipError_t group_c128_small_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
+{
+    switch (g.m) {
+    case 0: return extract_tiles_m<double2, 0>(g, b, tiles, s);
+    case 1: return extract_tiles_m<double2, 1>(g, b, tiles, s);
+    case 2: return extract_tiles_m<double2, 2>(g, b, tiles, s);
+    case 3: return extract_tiles_m<double2, 3>(g, b, tiles, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t group_c128_small_emit_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
+{
+    switch (g.m) {
+    case 0: return emit_tiles_m<double2, 0>(g, b, tiles, s);
+    case 1: return emit_tiles_m<double2, 1>(g, b, tiles, s);
+    case 2: return emit_tiles_m<double2, 2>(g, b, tiles, s);
+    case 3: return emit_tiles_m<double2, 3>(g, b, tiles, s);
+    }
+    return hipErrorInvalidValue;
+}

@@ -22,3 +22,12 @@ hipError_t group_c64_large_compact(int kind, const GateArg &g, const PassBufs &b
     }
     return hipErrorInvalidValue;
 }
+
+int group_c64_large_hist_capacity(int m)
+{
+    switch (m) {
+    case 4: return hist_capacity<float2, 4>();
+    case 5: return hist_capacity<float2, 5>();
+    }
+    return 1;
+}

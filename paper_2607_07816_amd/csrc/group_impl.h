@@ -45,10 +45,20 @@ template <int M> __device__ __forceinline__ u32 extract_bits(u64 key, const Gate
 
 template <int M> __device__ __forceinline__ u64 deposit_bits(u32 i, const GateArg &g)
 {
+    if (M <= 3) return g.dep[i];
     u64 k = 0;
 #pragma unroll
     for (int t = 0; t < M; ++t) k |= (u64)((i >> t) & 1u) << g.q[t];
     return k;
+}
+
+template <typename AT, int M> __device__ __forceinline__ void group_clear(Group<AT, M> &G)
+{
+#pragma unroll
+    for (int jj = 0; jj < (1 << M); ++jj) {
+        G.v[jj].x = 0;
+        G.v[jj].y = 0;
+    }
 }
 
 template <typename AT, int M> __device__ __forceinline__ void group_set(Group<AT, M> &G, u32 j, AT a)
@@ -85,6 +95,7 @@ __device__ __forceinline__ void load_group(const GateArg &g, const u64 *__restri
         if (mp == rest) return; // an earlier member leads this group
     }
     G.rest = rest;
+    group_clear<AT, M>(G);
     group_set<AT, M>(G, extract_bits<M>(key, g), amp);
     for (u64 p = idx + 1; p < n; ++p) {
         const u64 kp = keys[p];
@@ -94,17 +105,29 @@ __device__ __forceinline__ void load_group(const GateArg &g, const u64 *__restri
     }
 }
 
-template <int M> __device__ __forceinline__ double u_re(const GateArg &g, int i, int j)
-{
-    if (M <= 3) return g.ur[i * (1 << M) + j];
-    return g.uptr[2 * (i * (1 << M) + j)];
-}
-
-template <int M> __device__ __forceinline__ double u_im(const GateArg &g, int i, int j)
-{
-    if (M <= 3) return g.ui[i * (1 << M) + j];
-    return g.uptr[2 * (i * (1 << M) + j) + 1];
-}
+// entry U[i][j] in the arithmetic type R of the amplitudes (FP32 entries
+// were rounded once on the host; m >= 4 reads the FP64 copy in device memory)
+template <typename R, int M> struct UEntry;
+template <int M> struct UEntry<double, M> {
+    static __device__ __forceinline__ double re(const GateArg &g, int i, int j)
+    {
+        return M <= 3 ? g.ur[i * (1 << M) + j] : g.uptr[2 * (i * (1 << M) + j)];
+    }
+    static __device__ __forceinline__ double im(const GateArg &g, int i, int j)
+    {
+        return M <= 3 ? g.ui[i * (1 << M) + j] : g.uptr[2 * (i * (1 << M) + j) + 1];
+    }
+};
+template <int M> struct UEntry<float, M> {
+    static __device__ __forceinline__ float re(const GateArg &g, int i, int j)
+    {
+        return M <= 3 ? g.fr[i * (1 << M) + j] : (float)g.uptr[2 * (i * (1 << M) + j)];
+    }
+    static __device__ __forceinline__ float im(const GateArg &g, int i, int j)
+    {
+        return M <= 3 ? g.fi[i * (1 << M) + j] : (float)g.uptr[2 * (i * (1 << M) + j) + 1];
+    }
+};
 
 // new amplitude with local pattern i of the group
 template <typename AT, int M>
@@ -113,16 +136,35 @@ __device__ __forceinline__ AT group_out(const GateArg &g, const Group<AT, M> &G,
     typedef typename Scalar<AT>::T R;
     if (M == 0) return G.v[0];
     R ar = (R)0, ai = (R)0;
+    if (sizeof(R) == 4) {
+        // complex64: fused multiply-adds (the FP32 path is held to a
+        // tolerance, not to the FP64 operation order); absent members are
+        // zero and add nothing
 #pragma unroll Unroll<M>::value
-    for (int j = 0; j < (1 << M); ++j) {
-        if ((G.present >> j) & 1u) {
-            const R ur = (R)u_re<M>(g, i, j);
-            const R ui = (R)u_im<M>(g, i, j);
+        for (int j = 0; j < (1 << M); ++j) {
+            const R ur = UEntry<R, M>::re(g, i, j);
+            const R ui = UEntry<R, M>::im(g, i, j);
+            const R vr = G.v[j].x, vi = G.v[j].y;
+            ar = __builtin_fmaf(ur, vr, ar);
+            ar = __builtin_fmaf(-ui, vi, ar);
+            ai = __builtin_fmaf(ur, vi, ai);
+            ai = __builtin_fmaf(ui, vr, ai);
+        }
+    } else {
+        // complex128: the oracle's order - each product and sum rounded once,
+        // members summed in ascending j; an absent member leaves the sum
+        // untouched (selected away, not added as zero, so signed zeros match)
+#pragma unroll Unroll<M>::value
+        for (int j = 0; j < (1 << M); ++j) {
+            const R ur = UEntry<R, M>::re(g, i, j);
+            const R ui = UEntry<R, M>::im(g, i, j);
             const R vr = G.v[j].x, vi = G.v[j].y;
             const R tr = ur * vr - ui * vi;
             const R ti = ur * vi + ui * vr;
-            ar = ar + tr;
-            ai = ai + ti;
+            const R nr = ar + tr, ni = ai + ti;
+            const bool has = (G.present >> j) & 1u;
+            ar = has ? nr : ar;
+            ai = has ? ni : ai;
         }
     }
     AT o;
@@ -260,8 +302,12 @@ __global__ void __launch_bounds__(STS_WG) k_group_compact(GateArg g, PassBufs b)
     if (tile >= ntiles) {
         if (tile == 0) { // empty input: publish the empty result
             if (tid == 0) {
-                if (KIND == STS_KIND_EXTRACT) ctl->side_n = 0;
-                else *b.n_out = 0;
+                if (KIND == STS_KIND_EXTRACT) {
+                    ctl->side_n = 0;
+                    ctl->side_dense = 1;
+                } else {
+                    *b.n_out = 0;
+                }
             }
         }
         return;
@@ -298,8 +344,12 @@ __global__ void __launch_bounds__(STS_WG) k_group_compact(GateArg g, PassBufs b)
     const u64 base = s_base + my_off;
     if (tid == 0 && tile == ntiles - 1) {
         const u64 total = base + tile_total;
-        if (KIND == STS_KIND_EXTRACT) ctl->side_n = total;
-        else *b.n_out = total;
+        if (KIND == STS_KIND_EXTRACT) {
+            ctl->side_n = total;
+            ctl->side_dense = 1;
+        } else {
+            *b.n_out = total;
+        }
     }
     if (mine == 0) return;
 
@@ -340,19 +390,562 @@ __global__ void __launch_bounds__(STS_WG) k_group_compact(GateArg g, PassBufs b)
     }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-tiled passes (gates of up to 3 qubits). A workgroup stages a tile of
+// TT_TG sorted terms plus a halo of TT_H on each side (keys, amplitudes and
+// hash buckets) in LDS, so the partner search reads LDS; a run that crosses
+// the halo continues in global memory. Compaction passes claim TT_BATCH
+// consecutive tiles per atomic; a batch of more than one tile serialises the
+// look-back (a batch's first tile waits for the previous batch's last).
+// ---------------------------------------------------------------------------
+constexpr int TT_IT = 8;
+constexpr int TT_TG = STS_WG * TT_IT;   // 2048 terms per tile
+constexpr int TT_H = 64;
+constexpr int TT_LD = TT_TG + 2 * TT_H;
+constexpr int TT_BATCH = 1;
+constexpr int TT_EBASE = 1023 - 127 + 8; // exponent fields [904, 1032) live in LDS bins
+constexpr int TT_NB = 128;
+
+template <typename AT> struct TileSmem {
+    u64 key[TT_LD];
+    AT amp[TT_LD];
+    u32 bkt[TT_LD];
+};
+
+// stage global terms [lo, hi) into LDS: every load of the thread is issued
+// before any of them is used, so the tile costs one memory latency, not nine
+template <typename AT, int M>
+__device__ __forceinline__ void stage_tile(TileSmem<AT> &s, const GateArg &g, const u64 *__restrict__ keys,
+                                           const AT *__restrict__ amps, u64 lo, u64 hi)
+{
+    constexpr int PER = (TT_LD + STS_WG - 1) / STS_WG;
+    const int sh = 64 - g.hb;
+    u64 kk[PER];
+    AT aa[PER];
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const u64 i = lo + (u64)r * STS_WG + threadIdx.x;
+        if (i < hi) {
+            kk[r] = keys[i];
+            aa[r] = amps[i];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+        const u64 i = lo + (u64)r * STS_WG + threadIdx.x;
+        if (i < hi) {
+            const int li = r * STS_WG + (int)threadIdx.x;
+            s.key[li] = kk[r];
+            s.amp[li] = aa[r];
+            if (M > 0) s.bkt[li] = (u32)(sts_mix64(kk[r] & g.notmask) >> sh);
+        }
+    }
+}
+
+// the group led by term e (global index), from the staged tile [lo, hi)
+template <typename AT, int M>
+__device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg &g, const u64 *__restrict__ keys,
+                                           const AT *__restrict__ amps, u64 lo, u64 hi, u64 n, u64 e,
+                                           Group<AT, M> &G)
+{
+    G.present = 0;
+    G.rest = 0;
+    if (e >= n) return;
+    const int li = (int)(e - lo);
+    const u64 key = s.key[li];
+    const AT amp = s.amp[li];
+    if (M == 0) {
+        G.rest = key;
+        G.v[0] = amp;
+        G.present = 1;
+        return;
+    }
+    const u64 rest = key & g.notmask;
+    const u32 b = s.bkt[li];
+    const int sh = 64 - g.hb;
+    for (u64 p = e; p > 0; --p) {
+        const u64 q = p - 1;
+        u64 kq;
+        u32 bq;
+        if (q >= lo) {
+            kq = s.key[q - lo];
+            bq = s.bkt[q - lo];
+        } else {
+            kq = keys[q];
+            bq = (u32)(sts_mix64(kq & g.notmask) >> sh);
+        }
+        if (bq != b) break;
+        if ((kq & g.notmask) == rest) return; // an earlier member leads
+    }
+    G.rest = rest;
+    group_clear<AT, M>(G);
+    group_set<AT, M>(G, extract_bits<M>(key, g), amp);
+    for (u64 q = e + 1; q < n; ++q) {
+        const bool in = q < hi;
+        u64 kq;
+        u32 bq;
+        if (in) {
+            kq = s.key[q - lo];
+            bq = s.bkt[q - lo];
+        } else {
+            kq = keys[q];
+            bq = (u32)(sts_mix64(kq & g.notmask) >> sh);
+        }
+        if (bq != b) break;
+        if ((kq & g.notmask) == rest) group_set<AT, M>(G, extract_bits<M>(kq, g), in ? s.amp[q - lo] : amps[q]);
+    }
+}
+
+// position of this lane's item among the lanes of its wave that keep one,
+// plus a base claimed once per wave from an LDS counter
+__device__ __forceinline__ u32 wave_claim(bool keep, u32 *counter)
+{
+    const u64 mask = __ballot(keep);
+    if (!mask) return 0;
+    const int leader = __ffsll((long long)mask) - 1;
+    u32 base = 0;
+    if (sts_lane() == leader) base = atomicAdd(counter, (u32)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    return base + (u32)__popcll(mask & sts_lanemask_lt());
+}
+
+// LDS bins of the histogram pass: TT_NB exponent fields from TT_EBASE, in
+// TT_COPIES copies (lane % TT_COPIES picks one) so that lanes hitting the same
+// hot exponent do not all serialise on one address
+constexpr int TT_COPIES = 4;
+
+// add the LDS bins to the global exponent histogram and clear them
+__device__ __forceinline__ void flush_bins(const PassBufs &b, u64 *s_hi, u64 *s_lo)
+{
+    for (int i = threadIdx.x; i < TT_NB; i += STS_WG) {
+        u64 hi = 0, lo = 0;
+#pragma unroll
+        for (int c = 0; c < TT_COPIES; ++c) {
+            hi += s_hi[c * TT_NB + i];
+            lo += s_lo[c * TT_NB + i];
+            s_hi[c * TT_NB + i] = 0;
+            s_lo[c * TT_NB + i] = 0;
+        }
+        const u64 cnt = lo >> 44;
+        if (cnt) {
+            const int e_ = TT_EBASE + i;
+            atomicAdd(&b.h1[e_], cnt);
+            atomicAdd(&b.h1[STS_NBIN + e_], hi);
+            atomicAdd(&b.h1[2 * STS_NBIN + e_], lo & ((1ull << 44) - 1));
+        }
+    }
+}
+
+// histogram pass over tiles (static tile assignment, persistent grid). With
+// b.predict, the candidates whose exponent field equals the previous step's
+// cut exponent (ctl->e_pred) also go to the tile's side-buffer slab, and the
+// tile's candidates above it are counted: when this step's cut exponent turns
+// out the same, the extraction pass has nothing left to do.
+template <typename AT, int M>
+__global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
+{
+    __shared__ TileSmem<AT> s;
+    __shared__ u64 s_hi[TT_COPIES * TT_NB]; // sum of mantissa >> 26
+    __shared__ u64 s_lo[TT_COPIES * TT_NB]; // sum of mantissa & (2^26-1), plus count << 44
+    __shared__ u64 s_bw[STS_WG / 64], s_bk[STS_WG / 64];
+    __shared__ u32 s_above, s_side;
+    for (int i = threadIdx.x; i < TT_COPIES * TT_NB; i += STS_WG) {
+        s_hi[i] = 0;
+        s_lo[i] = 0;
+    }
+    DevCtl *ctl = b.ctl;
+    const u64 n = *b.n_in;
+    const u64 *keys = b.keys;
+    const AT *amps = (const AT *)b.amps;
+    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
+    const int e_pred = b.predict ? ctl->e_pred : -1;
+    const bool predict = e_pred >= 0;
+    if (predict && blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->side_dense = 0;
+        ctl->side_ntiles = ntiles;
+        ctl->side_slab_shift = 11 + M;
+    }
+    const int copy = (int)(threadIdx.x % TT_COPIES) * TT_NB;
+    u64 bw = 0, bk = ~0ull;
+    int since_flush = 0;
+    for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (since_flush == 8) {
+            // a tile adds at most 2048 * 8 candidates to a bin, so after 8 tiles
+            // the low sums stay below 2^43 and the counts below 2^17: flush
+            __syncthreads();
+            flush_bins(b, s_hi, s_lo);
+            since_flush = 0;
+        }
+        ++since_flush;
+        const u64 base = tile * TT_TG;
+        const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
+        const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
+        __syncthreads(); // previous tile done with the LDS
+        if (threadIdx.x == 0) {
+            s_above = 0;
+            s_side = 0;
+        }
+        stage_tile<AT, M>(s, g, keys, amps, lo, hi);
+        __syncthreads();
+        const u64 slab = tile << (11 + M);
+        u32 above = 0;
+#pragma unroll 1
+        for (int k = 0; k < TT_IT; ++k) {
+            const u64 e = base + (u64)k * STS_WG + threadIdx.x;
+            Group<AT, M> G;
+            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+#pragma unroll Unroll<M>::value
+            for (int i = 0; i < (1 << M); ++i) {
+                const AT o = group_out<AT, M>(g, G, i);
+                const bool cand = G.present && (M == 0 || nonzero(o));
+                const u64 wb = weight_bits(o);
+                const int e_ = (int)(wb >> 52);
+                const u64 key = G.rest | deposit_bits<M>((u32)i, g);
+                if (predict) {
+                    above += (cand && e_ > e_pred) ? 1u : 0u;
+                    const bool side = cand && e_ == e_pred;
+                    const u32 at = wave_claim(side, &s_side);
+                    if (side && slab + at < b.side_cap) {
+                        b.side_key[slab + at] = key;
+                        b.side_w[slab + at] = wb;
+                    }
+                }
+                if (!cand) continue;
+                const u64 mant = sts_mant(wb);
+                const int bin = e_ - TT_EBASE;
+                if (bin >= 0 && bin < TT_NB) {
+                    atomicAdd(&s_hi[copy + bin], mant >> 26);
+                    atomicAdd(&s_lo[copy + bin], (mant & ((1ull << 26) - 1)) | (1ull << 44));
+                } else { // far outside the usual range: straight to the global bins
+                    atomicAdd(&b.h1[e_], 1ull);
+                    atomicAdd(&b.h1[STS_NBIN + e_], mant >> 26);
+                    atomicAdd(&b.h1[2 * STS_NBIN + e_], mant & ((1ull << 26) - 1));
+                }
+                const u64 tagged = wb | (1ull << 63);
+                if (tagged > bw || (tagged == bw && key < bk)) {
+                    bw = tagged;
+                    bk = key;
+                }
+            }
+        }
+        if (predict) {
+            atomicAdd(&s_above, above);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                b.t_above[tile] = s_above;
+                b.t_side[tile] = s_side;
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        const u64 ow = __shfl_xor(bw, d, 64);
+        const u64 ok = __shfl_xor(bk, d, 64);
+        if (ow > bw || (ow == bw && ok < bk)) {
+            bw = ow;
+            bk = ok;
+        }
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        s_bw[threadIdx.x >> 6] = bw;
+        s_bk[threadIdx.x >> 6] = bk;
+    }
+    flush_bins(b, s_hi, s_lo);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 w = s_bw[0], k = s_bk[0];
+        for (int i = 1; i < STS_WG / 64; ++i) {
+            if (s_bw[i] > w || (s_bw[i] == w && s_bk[i] < k)) {
+                w = s_bw[i];
+                k = s_bk[i];
+            }
+        }
+        b.best[blockIdx.x] = w;
+        b.best[STS_MAX_GROUPS + blockIdx.x] = k;
+    }
+}
+
+// compaction passes over tiles: EXTRACT (side buffer) or EMIT (new state)
+template <typename AT, int M, int KIND>
+__global__ void __launch_bounds__(STS_WG) k_tile_compact(GateArg g, PassBufs b)
+{
+    typedef typename Scalar<AT>::T R;
+    __shared__ TileSmem<AT> s;
+    __shared__ u32 s_tile;
+    __shared__ u32 s_scratch[STS_WG / 64];
+    __shared__ u64 s_base;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        const u32 t = atomicAdd(b.tile_ctr, (u32)TT_BATCH);
+        if (t == (gridDim.x - 1) * TT_BATCH) st_agent(b.tile_ctr, 0u); // last claim: reset
+        s_tile = t;
+    }
+    __syncthreads();
+    const u64 first_tile = s_tile;
+    DevCtl *ctl = b.ctl;
+    const int materialise = b.materialise;
+    if (KIND == STS_KIND_EXTRACT && ctl->keep_all) return;
+    const u64 n = *b.n_in;
+    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
+    if (first_tile >= ntiles) {
+        if (first_tile == 0 && tid == 0) { // empty input: publish the empty result
+            if (KIND == STS_KIND_EXTRACT) ctl->side_n = 0;
+            else *b.n_out = 0;
+        }
+        return;
+    }
+    const bool keep_everything = KIND == STS_KIND_EMIT && (materialise || ctl->keep_all);
+    const int e_star = ctl->e_star;
+    const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
+    const bool rescale = KIND == STS_KIND_EMIT && !materialise && !ctl->keep_all && ctl->dropped;
+    const double scale = ctl->scale;
+    const u64 *keys = b.keys;
+    const AT *amps = (const AT *)b.amps;
+    const u64 cap = KIND == STS_KIND_EXTRACT ? b.side_cap : b.out_cap;
+
+    for (u64 tile = first_tile; tile < first_tile + TT_BATCH && tile < ntiles; ++tile) {
+        const u64 base = tile * TT_TG;
+        const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
+        const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
+        __syncthreads();
+        stage_tile<AT, M>(s, g, keys, amps, lo, hi);
+        __syncthreads();
+        // count
+        u32 mine = 0;
+#pragma unroll 1
+        for (int k = 0; k < TT_IT; ++k) {
+            const u64 e = base + (u64)k * STS_WG + tid;
+            Group<AT, M> G;
+            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+            if (!G.present) continue;
+#pragma unroll Unroll<M>::value
+            for (int i = 0; i < (1 << M); ++i) {
+                const AT o = group_out<AT, M>(g, G, i);
+                const u64 key = G.rest | deposit_bits<M>((u32)i, g);
+                const bool keep = keep_everything ? (M == 0 || nonzero(o))
+                                                  : keep_out<AT, M, KIND>(ctl, materialise, o, key, e_star, thr_w,
+                                                                          thr_k);
+                mine += keep ? 1u : 0u;
+            }
+        }
+        u32 tile_total;
+        const u32 my_off = block_excl_scan<u32, STS_WG>(mine, s_scratch, &tile_total);
+        if (tid == 0) s_base = lb_exclusive(b.look, 1, tile, tile_total, b.epoch);
+        __syncthreads();
+        u64 pos = s_base + my_off;
+        if (tid == 0 && tile == ntiles - 1) {
+            const u64 total = s_base + tile_total;
+            if (KIND == STS_KIND_EXTRACT) ctl->side_n = total;
+            else *b.n_out = total;
+        }
+        if (mine == 0) continue;
+        // write
+#pragma unroll 1
+        for (int k = 0; k < TT_IT; ++k) {
+            const u64 e = base + (u64)k * STS_WG + tid;
+            Group<AT, M> G;
+            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+            if (!G.present) continue;
+#pragma unroll Unroll<M>::value
+            for (int i = 0; i < (1 << M); ++i) {
+                AT o = group_out<AT, M>(g, G, i);
+                const u64 key = G.rest | deposit_bits<M>((u32)i, g);
+                const bool keep = keep_everything ? (M == 0 || nonzero(o))
+                                                  : keep_out<AT, M, KIND>(ctl, materialise, o, key, e_star, thr_w,
+                                                                          thr_k);
+                if (!keep) continue;
+                if (pos >= cap) {
+                    atomicOr(&ctl->flags, KIND == STS_KIND_EXTRACT ? STS_F_SIDE_OVERFLOW : STS_F_OUT_OVERFLOW);
+                    ++pos;
+                    continue;
+                }
+                if (KIND == STS_KIND_EXTRACT) {
+                    b.side_key[pos] = key;
+                    b.side_w[pos] = weight_bits(o);
+                } else {
+                    if (rescale) {
+                        o.x = (R)((double)o.x * scale);
+                        o.y = (R)((double)o.y * scale);
+                    }
+                    b.out_keys[pos] = key;
+                    ((AT *)b.out_amps)[pos] = o;
+                }
+                ++pos;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// atomic-free compaction (gates of up to 3 qubits), one workgroup per tile:
+//   k_tile_extract - counts the tile's candidates ranked certainly before the
+//                    cut (exponent field above e*, or all when nothing is
+//                    cut) and copies those of exponent e* into the tile's own
+//                    slab of the side buffer (2048 << m entries per tile)
+//   (then: per-tile survivor counts, a scan into offsets - select.hip)
+//   k_tile_emit    - writes the tile's survivors at its offset
+// ---------------------------------------------------------------------------
+template <typename AT, int M>
+__global__ void __launch_bounds__(STS_WG) k_tile_extract(GateArg g, PassBufs b)
+{
+    __shared__ TileSmem<AT> s;
+    __shared__ u32 s_above, s_side;
+    const int tid = threadIdx.x;
+    DevCtl *ctl = b.ctl;
+    const u64 n = *b.n_in;
+    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
+    const u64 tile = blockIdx.x;
+    if (!b.materialise && ctl->pred_hit) return; // the histogram pass already did this
+    if (tile == 0 && tid == 0) {
+        ctl->side_dense = 0;
+        ctl->side_ntiles = ntiles;
+        ctl->side_slab_shift = 11 + M;
+    }
+    if (tile >= ntiles) return;
+    const bool all = b.materialise || ctl->keep_all;
+    const int e_star = ctl->e_star;
+    const u64 *keys = b.keys;
+    const AT *amps = (const AT *)b.amps;
+    const u64 base = tile * TT_TG;
+    const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
+    const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
+    if (tid == 0) {
+        s_above = 0;
+        s_side = 0;
+    }
+    stage_tile<AT, M>(s, g, keys, amps, lo, hi);
+    __syncthreads();
+    const u64 slab = tile << (11 + M);
+    u32 above = 0;
+#pragma unroll 1
+    for (int k = 0; k < TT_IT; ++k) {
+        const u64 e = base + (u64)k * STS_WG + tid;
+        Group<AT, M> G;
+        tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+#pragma unroll Unroll<M>::value
+        for (int i = 0; i < (1 << M); ++i) {
+            const AT o = group_out<AT, M>(g, G, i);
+            const bool cand = G.present && (M == 0 || nonzero(o));
+            const u64 wb = weight_bits(o);
+            const int ex = (int)(wb >> 52);
+            above += (cand && (all || ex > e_star)) ? 1u : 0u;
+            const bool side = cand && !all && ex == e_star;
+            const u32 at = wave_claim(side, &s_side);
+            if (side && slab + at < b.side_cap) {
+                b.side_key[slab + at] = G.rest | deposit_bits<M>((u32)i, g);
+                b.side_w[slab + at] = wb;
+            }
+        }
+    }
+    atomicAdd(&s_above, above);
+    __syncthreads();
+    if (tid == 0) {
+        b.t_above[tile] = s_above;
+        b.t_side[tile] = s_side;
+    }
+}
+
+template <typename AT, int M>
+__global__ void __launch_bounds__(STS_WG) k_tile_emit(GateArg g, PassBufs b)
+{
+    typedef typename Scalar<AT>::T R;
+    __shared__ TileSmem<AT> s;
+    __shared__ u32 s_out;
+    const int tid = threadIdx.x;
+    DevCtl *ctl = b.ctl;
+    const u64 n = *b.n_in;
+    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
+    const u64 tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const bool all = b.materialise || ctl->keep_all;
+    const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
+    const bool rescale = !all && ctl->dropped;
+    const double scale = ctl->scale;
+    const u64 *keys = b.keys;
+    const AT *amps = (const AT *)b.amps;
+    const u64 base = tile * TT_TG;
+    const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
+    const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
+    if (tid == 0) s_out = 0;
+    stage_tile<AT, M>(s, g, keys, amps, lo, hi);
+    __syncthreads();
+    const u64 out0 = b.t_off[tile];
+#pragma unroll 1
+    for (int k = 0; k < TT_IT; ++k) {
+        const u64 e = base + (u64)k * STS_WG + tid;
+        Group<AT, M> G;
+        tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+#pragma unroll Unroll<M>::value
+        for (int i = 0; i < (1 << M); ++i) {
+            AT o = group_out<AT, M>(g, G, i);
+            const u64 key = G.rest | deposit_bits<M>((u32)i, g);
+            const u64 wb = weight_bits(o);
+            const bool keep = G.present && (M == 0 || nonzero(o)) &&
+                              (all || wb > thr_w || (wb == thr_w && key <= thr_k));
+            const u32 at = wave_claim(keep, &s_out);
+            if (keep && out0 + at < b.out_cap) {
+                if (rescale) {
+                    o.x = (R)((double)o.x * scale);
+                    o.y = (R)((double)o.y * scale);
+                }
+                b.out_keys[out0 + at] = key;
+                ((AT *)b.out_amps)[out0 + at] = o;
+            }
+        }
+    }
+}
+
+// workgroups of the histogram pass that fit on the device at once (the pass
+// is persistent: more would run as a second, mostly idle wave)
+template <typename AT, int M> int hist_capacity()
+{
+    static int cap = 0;
+    if (!cap) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (M <= 3) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_hist<AT, M>, STS_WG, 0);
+        else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_group_hist<AT, M>, STS_WG, 0);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        cap = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    }
+    return cap;
+}
+
 template <typename AT, int M> hipError_t hist_m(const GateArg &g, const PassBufs &b, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_group_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
+    if (M <= 3) hipLaunchKernelGGL((k_tile_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
+    else hipLaunchKernelGGL((k_group_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
     return hipGetLastError();
 }
 
 template <typename AT, int M>
 hipError_t compact_m(int kind, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
+    if (M <= 3) {
+        // tiles: launched workgroups, each claiming TT_BATCH tiles of TT_TG terms
+        if (kind == STS_KIND_EXTRACT)
+            hipLaunchKernelGGL((k_tile_compact<AT, M, STS_KIND_EXTRACT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+        else
+            hipLaunchKernelGGL((k_tile_compact<AT, M, STS_KIND_EMIT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+        return hipGetLastError();
+    }
     if (kind == STS_KIND_EXTRACT)
         hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EXTRACT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
     else
         hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EMIT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+    return hipGetLastError();
+}
+
+template <typename AT, int M> hipError_t extract_tiles_m(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tile_extract<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+    return hipGetLastError();
+}
+
+template <typename AT, int M> hipError_t emit_tiles_m(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tile_emit<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
     return hipGetLastError();
 }
 

@@ -18,6 +18,9 @@ struct GateArg {
     int pad;
     double ur[64];      // row-major U, real parts (m <= 3)
     double ui[64];      // imaginary parts
+    float fr[64];       // the same rounded to FP32 (nearest-even), for complex64 states
+    float fi[64];
+    u64 dep[8];         // dep[i]: pattern i deposited on the gate's qubits (m <= 3)
     const double *uptr; // m >= 4
 };
 
@@ -41,29 +44,49 @@ struct PassBufs {
     u64 *out_keys;        // new state
     void *out_amps;
     u64 out_cap;
+    u32 *t_above;         // per tile: survivors certain before the cut (tiled passes)
+    u32 *t_side;          // per tile: side-buffer entries in the tile's slab
+    u64 *t_off;           // per tile: output offset of its survivors
     u64 *look;            // look-back words, one per tile
     u32 *tile_ctr;
     u32 epoch;            // tags look-back words of this launch
     int materialise;      // 1: keep every candidate, no rescale (no truncation)
+    int predict;          // histogram pass: also extract the predicted cut exponent
 };
 
 // launch helpers (return hipError_t of the launch)
 hipError_t launch_radix_hist(const u64 *keys, const u64 *n_in, u64 notmask, int hb, int npass,
                              u64 *hist, int grid, hipStream_t s);
-hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, hipStream_t s);
+hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, u32 *epoch, hipStream_t s);
 hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout,
                              const u64 *n_in, u64 *n_out, u64 notmask, int shift, const u64 *offs,
-                             u64 *look, u32 *tile_ctr, u32 epoch, int tiles, hipStream_t s);
+                             u64 *look, u32 *tile_ctr, const u32 *epoch_base, int pass, int tiles,
+                             hipStream_t s);
 
 hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, hipStream_t s);
+int group_hist_capacity(int prec, int m); // resident workgroups of the histogram pass
 hipError_t launch_group_compact(int prec, int kind, const GateArg &g, const PassBufs &b, int tiles,
                                 hipStream_t s);
-hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, hipStream_t s);
+hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, int predicted, hipStream_t s);
 hipError_t launch_side_hist(const PassBufs &b, u64 *h2, int grid, hipStream_t s);
 hipError_t launch_side_extract(const PassBufs &b, int grid, hipStream_t s);
+hipError_t launch_tile_kept(const PassBufs &b, int tiles, hipStream_t s);
+hipError_t launch_tile_scan(const PassBufs &b, u64 ntiles_bound, hipStream_t s);
+hipError_t launch_group_extract_tiles(int prec, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
+hipError_t launch_group_emit_tiles(int prec, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t launch_final(const PassBufs &b, hipStream_t s);
 hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s);
 hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s);
+
+// workgroups to launch for a compaction pass over n terms with an m-qubit
+// gate: m <= 3 uses LDS tiles of 2048 terms, larger
+// gates one tile of STS_GTILE terms per workgroup
+inline u64 sts_compact_groups(u64 n, int m)
+{
+    const u64 per = m <= 3 ? 2048ull : 1024ull;
+    const u64 g = (n + per - 1) / per;
+    return g ? g : 1;
+}
 
 #define STS_KIND_EXTRACT 0
 #define STS_KIND_EMIT 1

@@ -31,11 +31,23 @@ __global__ void __launch_bounds__(STS_WG) k_radix_hist(const u64 *__restrict__ k
     __syncthreads();
     const u64 n = *n_in;
     const int base_shift = 64 - hb;
-    for (u64 i = (u64)blockIdx.x * STS_WG + threadIdx.x; i < n; i += (u64)gridDim.x * STS_WG) {
-        const u64 h = sts_mix64(keys[i] & notmask);
-        for (int p = 0; p < npass; ++p) {
-            const u32 d = (u32)((h >> (base_shift + 8 * p)) & 255u);
-            atomicAdd(&s_h[p * 256 + d], 1u);
+    constexpr int IT = 8; // keys per thread per round, loaded before use
+    for (u64 r = (u64)blockIdx.x * STS_WG * IT; r < n; r += (u64)gridDim.x * STS_WG * IT) {
+        u64 kk[IT];
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const u64 i = r + (u64)k * STS_WG + threadIdx.x;
+            kk[k] = i < n ? keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const u64 i = r + (u64)k * STS_WG + threadIdx.x;
+            if (i >= n) continue;
+            const u64 h = sts_mix64(kk[k] & notmask);
+            for (int p = 0; p < npass; ++p) {
+                const u32 d = (u32)((h >> (base_shift + 8 * p)) & 255u);
+                atomicAdd(&s_h[p * 256 + d], 1u);
+            }
         }
     }
     __syncthreads();
@@ -45,10 +57,18 @@ __global__ void __launch_bounds__(STS_WG) k_radix_hist(const u64 *__restrict__ k
     }
 }
 
-// exclusive scan of each pass's 256 digit counts; clears the histogram
-__global__ void __launch_bounds__(256) k_radix_scan(u64 *__restrict__ hist, u64 *__restrict__ offs, int npass)
+// exclusive scan of each pass's 256 digit counts; clears the histogram and
+// advances the look-back tags (on the device, so a replayed graph of these
+// launches never meets tags of an earlier replay)
+__global__ void __launch_bounds__(256) k_radix_scan(u64 *__restrict__ hist, u64 *__restrict__ offs, int npass,
+                                                    u32 *epoch)
 {
     __shared__ u64 scratch[4];
+    if (threadIdx.x == 0) {
+        u32 e = *epoch + STS_MAX_PASSES;
+        if (e >= (1u << 24) - STS_MAX_PASSES) e = 1;
+        *epoch = e;
+    }
     for (int p = 0; p < npass; ++p) {
         const u64 v = hist[p * 256 + threadIdx.x];
         u64 tot;
@@ -63,7 +83,7 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
                                                         u64 *__restrict__ kout, AT *__restrict__ aout,
                                                         const u64 *n_in, u64 *n_out, u64 notmask, int shift,
                                                         const u64 *__restrict__ offs, u64 *__restrict__ look,
-                                                        u32 *tile_ctr, u32 epoch)
+                                                        u32 *tile_ctr, const u32 *epoch_base, int pass)
 {
     constexpr int NW = STS_WG / 64;
     constexpr int IT = STS_TILE_ITEMS;
@@ -92,16 +112,27 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     const u64 base = tile * STS_TILE;
     if (base >= n) return;
 
-    // rank every key of the tile among equal digits, in index order
+    // issue every key and amplitude load of the thread first
     u64 key[IT];
+    AT amp[IT];
     u32 dig[IT];
     u32 rank[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
+        if (e < n) {
+            key[k] = kin[e];
+            amp[k] = ain[e];
+        } else {
+            key[k] = 0ull;
+        }
+    }
+    // rank every key of the tile among equal digits, in index order
     const u64 lt = sts_lanemask_lt();
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
         const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
         const bool valid = e < n;
-        key[k] = valid ? kin[e] : 0ull;
         const u32 d = valid ? bucket_digit(key[k], notmask, shift) : 0u;
         dig[k] = valid ? d : 256u;
         u64 peers = __ballot(valid);
@@ -135,7 +166,7 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     const u32 dstart = block_excl_scan<u32, STS_WG>(tot, s_scratch, &all);
     s_dstart[tid] = dstart;
     // global position of this tile's first key with digit tid
-    const u64 excl = lb_exclusive(look + tid, 256, tile, tot, epoch);
+    const u64 excl = lb_exclusive(look + tid, 256, tile, tot, *epoch_base + (u32)pass);
     s_base[tid] = offs[tid] + excl;
     __syncthreads();
 
@@ -162,10 +193,7 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     AT *sa = reinterpret_cast<AT *>(s_buf);
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-        if (dig[k] < 256u) {
-            const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
-            sa[pos[k]] = ain[e];
-        }
+        if (dig[k] < 256u) sa[pos[k]] = amp[k];
     }
     __syncthreads();
     for (u32 i = tid; i < count; i += STS_WG) {
@@ -183,21 +211,21 @@ hipError_t launch_radix_hist(const u64 *keys, const u64 *n_in, u64 notmask, int 
     return hipGetLastError();
 }
 
-hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, hipStream_t s)
+hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, u32 *epoch, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, offs, npass);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, offs, npass, epoch);
     return hipGetLastError();
 }
 
 hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout, const u64 *n_in,
                              u64 *n_out, u64 notmask, int shift, const u64 *offs, u64 *look, u32 *tile_ctr,
-                             u32 epoch, int tiles, hipStream_t s)
+                             const u32 *epoch_base, int pass, int tiles, hipStream_t s)
 {
     if (prec == 0)
         hipLaunchKernelGGL(k_radix_pass<double2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const double2 *)ain,
-                           kout, (double2 *)aout, n_in, n_out, notmask, shift, offs, look, tile_ctr, epoch);
+                           kout, (double2 *)aout, n_in, n_out, notmask, shift, offs, look, tile_ctr, epoch_base, pass);
     else
         hipLaunchKernelGGL(k_radix_pass<float2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const float2 *)ain, kout,
-                           (float2 *)aout, n_in, n_out, notmask, shift, offs, look, tile_ctr, epoch);
+                           (float2 *)aout, n_in, n_out, notmask, shift, offs, look, tile_ctr, epoch_base, pass);
     return hipGetLastError();
 }

@@ -29,7 +29,7 @@ __device__ __forceinline__ u128 make128(u64 lo, u64 hi) { return ((u128)hi << 64
 // level 1: one workgroup of 256 threads. Thread t owns the eight exponent
 // bins 2047-8t .. 2040-8t (descending weight order).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_only)
+__global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_only, int predicted)
 {
     __shared__ Big s_big[256];
     __shared__ u64 s_cnt[256];
@@ -196,11 +196,15 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
             ctl->S = ctl->W;
             ctl->frac = 1.0;
             ctl->level = 1;
+            ctl->pred_hit = 0;
+            ctl->e_pred = -1;
         }
     } else if (hit == first) {
         const int e = 2047 - (int)first;
         const int k = (int)first - 8 * t;
         ctl->keep_all = 0;
+        ctl->pred_hit = (predicted && ctl->e_pred == e) ? 1 : 0;
+        ctl->e_pred = e;
         ctl->e_star = e;
         ctl->cnt_before = cnt_hit;
         ctl->S_excl = S_hit;
@@ -222,6 +226,74 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     }
     __syncthreads();
     for (int i = t; i < 3 * STS_NBIN; i += 256) h1[i] = 0;
+}
+
+// The side buffer is either dense (entries [0, side_n)) or split into one
+// slab of 2^shift entries per tile, slab t holding t_side[t] entries. Its
+// entries are visited through a flat index f over the whole layout.
+struct SideView {
+    const u64 *key;
+    const u64 *w;
+    const u32 *cnt;
+    u64 flat;  // flat indices to visit
+    int dense;
+    int shift;
+};
+
+__device__ __forceinline__ SideView side_view(const PassBufs &b, const DevCtl *ctl)
+{
+    SideView v;
+    v.key = b.side_key;
+    v.w = b.side_w;
+    v.cnt = b.t_side;
+    v.dense = ctl->side_dense;
+    v.shift = ctl->side_slab_shift;
+    const u64 f = v.dense ? ctl->side_n : (ctl->side_ntiles << v.shift);
+    v.flat = f < b.side_cap ? f : b.side_cap;
+    return v;
+}
+
+__device__ __forceinline__ bool side_valid(const SideView &v, u64 f)
+{
+    return v.dense || (f & ((1ull << v.shift) - 1)) < (u64)v.cnt[f >> v.shift];
+}
+
+// The same entries as a list of chunks: the slabs of the tiled layout, or
+// runs of 8192 entries of the dense one. Workgroups walk chunks; threads walk
+// the entries of a chunk.
+struct SideChunks {
+    u64 nchunks;
+    int dense;
+    int shift;
+    u64 n;          // dense: entries
+    u64 cap;
+    const u32 *cnt;
+};
+
+__device__ __forceinline__ SideChunks side_chunks(const PassBufs &b, const DevCtl *ctl)
+{
+    SideChunks c;
+    c.dense = ctl->side_dense;
+    c.shift = ctl->side_slab_shift;
+    c.cap = b.side_cap;
+    c.cnt = b.t_side;
+    c.n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
+    c.nchunks = c.dense ? (c.n + 8191) / 8192 : ctl->side_ntiles;
+    return c;
+}
+
+// first entry and entry count of chunk t
+__device__ __forceinline__ void chunk_range(const SideChunks &c, u64 t, u64 &base, u64 &count)
+{
+    if (c.dense) {
+        base = t * 8192;
+        count = c.n - base < 8192 ? c.n - base : 8192;
+    } else {
+        base = t << c.shift;
+        count = c.cnt[t];
+        if (base >= c.cap) count = 0;
+        else if (count > c.cap - base) count = c.cap - base;
+    }
 }
 
 // within-exponent rank key: ascending V = descending weight, then ascending key
@@ -376,15 +448,19 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
         s_lo[i] = 0;
     }
     __syncthreads();
-    const u64 n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
-    for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < n; i += (u64)gridDim.x * 256) {
-        const u64 wb = b.side_w[i];
-        const u64 vh = ((1ull << 52) - 1) - (wb & ((1ull << 52) - 1));
-        const u32 d = (u32)(vh >> 41);
-        const u64 mant = sts_mant(wb);
-        atomicAdd(&s_cnt[d], 1u);
-        atomicAdd(&s_hi[d], mant >> 26);
-        atomicAdd(&s_lo[d], mant & ((1ull << 26) - 1));
+    const SideChunks sc = side_chunks(b, ctl);
+    for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
+        u64 base, count;
+        chunk_range(sc, t, base, count);
+        for (u64 i = threadIdx.x; i < count; i += 256) {
+            const u64 wb = b.side_w[base + i];
+            const u64 vh = ((1ull << 52) - 1) - (wb & ((1ull << 52) - 1));
+            const u32 d = (u32)(vh >> 41);
+            const u64 mant = sts_mant(wb);
+            atomicAdd(&s_cnt[d], 1u);
+            atomicAdd(&s_hi[d], mant >> 26);
+            atomicAdd(&s_lo[d], mant & ((1ull << 26) - 1));
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
@@ -426,19 +502,27 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
     DevCtl *ctl = b.ctl;
     if (ctl->keep_all || (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
     if (ctl->sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
-    const u64 n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
+    const SideChunks sc = side_chunks(b, ctl);
     const int vshift = ctl->vshift;
     const u128 vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
     const u64 lt = sts_lanemask_lt();
-    const u64 stride = (u64)gridDim.x * 256;
-    for (u64 base = (u64)blockIdx.x * 256; base < n; base += stride) {
-        const u64 i = base + threadIdx.x;
+    for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x)
+    for (u64 i0 = 0;; i0 += 256) {
+        u64 cbase, count;
+        chunk_range(sc, t, cbase, count);
+        if (i0 >= count) break;
+        const u64 i = cbase + i0 + threadIdx.x;
         bool take = false;
         u64 w = 0, k = 0;
-        if (i < n) {
+        if (i0 + threadIdx.x < count) {
             w = b.side_w[i];
             k = b.side_key[i];
-            take = (rank_key(w, k) >> vshift) == vpre;
+            if (vshift >= 64) { // the fixed part lies in the weight half of V
+                const u64 vh = ((1ull << 52) - 1) - (w & ((1ull << 52) - 1));
+                take = (vh >> (vshift - 64)) == (u64)vpre;
+            } else {
+                take = (rank_key(w, k) >> vshift) == vpre;
+            }
         }
         const u64 mask = __ballot(take);
         if (!mask) continue;
@@ -481,7 +565,9 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     const bool small = ctl->sub_count <= b.sub_cap;
     const u64 *src_w = small ? b.sub_w : b.side_w;
     const u64 *src_k = small ? b.sub_key : b.side_key;
-    const u64 n = small ? ctl->sub_n : (ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap);
+    SideView view = side_view(b, ctl);
+    if (small) view.dense = 1;
+    const u64 n = small ? ctl->sub_n : view.flat;
     const u64 K = ctl->K;
     const u128 R = make128(ctl->R_lo, ctl->R_hi);
     if (t == 0) sub_load(s_sub, ctl);
@@ -495,6 +581,7 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
         __syncthreads();
         for (u64 i = t; i < n; i += FT) {
+            if (!side_valid(view, i)) continue;
             const u128 v = rank_key(src_w[i], src_k[i]);
             if ((v >> vshift) != vpre) continue;
             const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
@@ -516,6 +603,7 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     if (t == 0) s_n = 0;
     __syncthreads();
     for (u64 i = t; i < n; i += FT) {
+        if (!side_valid(view, i)) continue;
         const u128 v = rank_key(src_w[i], src_k[i]);
         if ((v >> vshift) != vpre) continue;
         const u32 slot = atomicAdd(&s_n, 1u);
@@ -613,6 +701,56 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     }
 }
 
+// ---------------------------------------------------------------------------
+// per-tile survivors of the tiled passes, then their exclusive scan
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
+{
+    __shared__ u32 s_scratch[4];
+    DevCtl *ctl = b.ctl;
+    const u64 n = *b.n_in;
+    const u64 ntiles = (n + 2047) / 2048;
+    const u64 tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
+    const int shift = ctl->side_slab_shift;
+    const u32 ns = b.t_side[tile];
+    u32 c = 0;
+    for (u32 i = threadIdx.x; i < ns; i += 256) {
+        const u64 at = (tile << shift) + i;
+        if (at >= b.side_cap) break;
+        const u64 wb = b.side_w[at], key = b.side_key[at];
+        c += (wb > thr_w || (wb == thr_w && key <= thr_k)) ? 1u : 0u;
+    }
+    u32 tot;
+    (void)block_excl_scan<u32, 256>(c, s_scratch, &tot);
+    if (threadIdx.x == 0) b.t_off[tile] = (u64)b.t_above[tile] + tot;
+}
+
+__global__ void __launch_bounds__(1024) k_tile_scan(PassBufs b)
+{
+    __shared__ u64 s_scratch[16];
+    DevCtl *ctl = b.ctl;
+    const u64 n = *b.n_in;
+    const u64 ntiles = (n + 2047) / 2048;
+    const u64 per = (ntiles + 1023) / 1024;
+    const u64 lo = threadIdx.x * per;
+    const u64 hi = lo + per < ntiles ? lo + per : ntiles;
+    u64 sum = 0;
+    for (u64 t = lo; t < hi; ++t) sum += b.t_off[t];
+    u64 total;
+    u64 run = block_excl_scan<u64, 1024>(sum, s_scratch, &total);
+    for (u64 t = lo; t < hi; ++t) {
+        const u64 c = b.t_off[t];
+        b.t_off[t] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) {
+        *b.n_out = total;
+        if (total > b.out_cap) atomicOr(&ctl->flags, STS_F_OUT_OVERFLOW);
+    }
+}
+
 __global__ void k_init_state(u64 *keys, double2 *amps64, float2 *amps32, u64 *n_out)
 {
     keys[0] = 0;
@@ -625,9 +763,9 @@ __global__ void k_set_n(u64 *n_out, u64 n) { *n_out = n; }
 
 } // namespace
 
-hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, hipStream_t s)
+hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, int predicted, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pick1, dim3(1), dim3(256), 0, s, b, groups, peak_only);
+    hipLaunchKernelGGL(k_pick1, dim3(1), dim3(256), 0, s, b, groups, peak_only, predicted);
     return hipGetLastError();
 }
 
@@ -640,6 +778,19 @@ hipError_t launch_side_hist(const PassBufs &b, u64 *h2, int grid, hipStream_t s)
 hipError_t launch_side_extract(const PassBufs &b, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_side_extract, dim3(grid), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_kept(const PassBufs &b, int tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tile_kept, dim3(tiles), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_scan(const PassBufs &b, u64 ntiles_bound, hipStream_t s)
+{
+    (void)ntiles_bound;
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, b);
     return hipGetLastError();
 }
 
