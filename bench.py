@@ -12,7 +12,11 @@ terms); the timed steps then continue the same circuit.
 metric: gate-term updates/s = (input terms of the timed steps) / time.
 roofline: the kernel kind with the largest share of the step time, its
 algorithmic bytes per launch over its average launch time (HIP events on the
-library's stream), against 8 TB/s.
+library's stream), against 8 TB/s. traffic: the HBM bytes per launch that
+rocprofv3's FETCH_SIZE and WRITE_SIZE counters recorded for that kernel
+(copy-calibrated, read from the committed summary under profiles/) over the
+same average launch time, in GB/s; null when the summary was taken on other
+kernels than the ones built.
 cpu_baseline: the C oracle (one thread) on one gate step of a bounded sample
 of the steady-state GPU state.
 """
@@ -57,8 +61,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=30, help="untimed gate steps before timing")
     ap.add_argument("--profile-steps", type=int, default=60, help="gate steps timed per kernel")
     ap.add_argument("--workload", default="48q", choices=["48q", "24q"])
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="terms in the CPU-baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="terms in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one device-to-device copy of BYTES (the reference dispatch that scales the "
+                         "FETCH_SIZE/WRITE_SIZE counters of a profiled run)")
     return ap.parse_args()
 
 
@@ -94,6 +101,14 @@ def main():
 
     torch.cuda.init()
     dev = torch.cuda.current_device()
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration} bytes done")
+        del src, dst
     log(f"device {torch.cuda.get_device_name(dev)}; workload {circuit.name} n={circuit.n} K={K} p={p} {prec}")
     st = State(circuit.n, K=K, p=p, precision=prec, capacity=K)
     gi = 0
@@ -152,6 +167,8 @@ def main():
                                       for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])))
     log(f"dominant {dom}: {avg_s * 1e6:.1f} us/launch, {per_launch / 1e6:.1f} MB/launch, {achieved:.0f} GB/s")
 
+    traffic_gbs = measured_traffic(dom, avg_s)
+
     key, prob = st.peak()
     log(f"state peak {key:#x} prob {prob:.4f} (hidden {circuit.hidden:#x})")
 
@@ -188,12 +205,31 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_gbs,
             "step_algorithmic_GBps": step_bytes / (total_ms / max(nsteps, 1) / 1e3) / 1e9 if total_ms else None,
         },
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic(kind: str, avg_s: float):
+    """HBM bytes per launch of `kind` from the committed counter summary,
+    over the live average launch time (GB/s); None if there is no summary for
+    that kernel or the library's kernels changed since it was taken."""
+    from paper_2607_07816_amd import profsum
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"{kind}_peaked48_K2e24_c64_hbm_traffic.txt")
+    if not os.path.exists(path) or avg_s <= 0:
+        return None
+    rec = profsum.read_traffic(path)
+    if rec.get("source_digest") != profsum.source_digest():
+        log(f"{os.path.basename(path)} was taken on other kernels: traffic not reported")
+        return None
+    tb = float(rec["traffic_bytes_per_launch"])
+    log(f"counter traffic of {kind}: {tb / 1e6:.1f} MB/launch")
+    return tb / avg_s / 1e9
 
 
 def cpu_baseline(st, circuit, gi, K, p, sample_terms):
