@@ -509,6 +509,27 @@ __device__ __forceinline__ u32 wave_claim(bool keep, u32 *counter)
     return base + (u32)__popcll(mask & sts_lanemask_lt());
 }
 
+// first of `cnt` consecutive slots for this lane (cnt < 2^BITS), the lanes of
+// the wave in lane order after a base claimed once per wave from an LDS
+// counter. Every lane of the wave must take part.
+template <int BITS> __device__ __forceinline__ u32 wave_claim_n(u32 cnt, u32 *counter)
+{
+    const u64 lt = sts_lanemask_lt();
+    u32 pre = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < BITS; ++bit) {
+        const u64 m = __ballot((cnt >> bit) & 1u);
+        pre += (u32)__popcll(m & lt) << bit;
+        tot += (u32)__popcll(m) << bit;
+    }
+    if (!tot) return 0;
+    const int leader = __ffsll((long long)__ballot(1)) - 1;
+    u32 base = 0;
+    if (sts_lane() == leader) base = atomicAdd(counter, tot);
+    base = __shfl(base, leader, 64);
+    return base + pre;
+}
+
 // LDS bins of the histogram pass: TT_NB exponent fields from TT_EBASE, in
 // TT_COPIES copies (lane % TT_COPIES picks one) so that lanes hitting the same
 // hot exponent do not all serialise on one address
@@ -594,21 +615,19 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
             const u64 e = base + (u64)k * STS_WG + threadIdx.x;
             Group<AT, M> G;
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+            u64 wbs[1 << M];
+            u32 sidebits = 0;
 #pragma unroll Unroll<M>::value
             for (int i = 0; i < (1 << M); ++i) {
                 const AT o = group_out<AT, M>(g, G, i);
                 const bool cand = G.present && (M == 0 || nonzero(o));
                 const u64 wb = weight_bits(o);
+                wbs[i] = wb;
                 const int e_ = (int)(wb >> 52);
                 const u64 key = G.rest | deposit_bits<M>((u32)i, g);
                 if (predict) {
                     above += (cand && e_ > e_pred) ? 1u : 0u;
-                    const bool side = cand && e_ == e_pred;
-                    const u32 at = wave_claim(side, &s_side);
-                    if (side && slab + at < b.side_cap) {
-                        b.side_key[slab + at] = key;
-                        b.side_w[slab + at] = wb;
-                    }
+                    sidebits |= (cand && e_ == e_pred) ? (1u << i) : 0u;
                 }
                 if (!cand) continue;
                 const u64 mant = sts_mant(wb);
@@ -625,6 +644,18 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
                 if (tagged > bw || (tagged == bw && key < bk)) {
                     bw = tagged;
                     bk = key;
+                }
+            }
+            if (predict) {
+                u32 at = wave_claim_n<M + 1>((u32)__popc(sidebits), &s_side);
+#pragma unroll Unroll<M>::value
+                for (int i = 0; i < (1 << M); ++i) {
+                    if (!((sidebits >> i) & 1u)) continue;
+                    if (slab + at < b.side_cap) {
+                        b.side_key[slab + at] = G.rest | deposit_bits<M>((u32)i, g);
+                        b.side_w[slab + at] = wbs[i];
+                    }
+                    ++at;
                 }
             }
         }
@@ -823,19 +854,27 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(GateArg g, PassBufs b)
         const u64 e = base + (u64)k * STS_WG + tid;
         Group<AT, M> G;
         tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+        u64 wbs[1 << M];
+        u32 sidebits = 0;
 #pragma unroll Unroll<M>::value
         for (int i = 0; i < (1 << M); ++i) {
             const AT o = group_out<AT, M>(g, G, i);
             const bool cand = G.present && (M == 0 || nonzero(o));
             const u64 wb = weight_bits(o);
+            wbs[i] = wb;
             const int ex = (int)(wb >> 52);
             above += (cand && (all || ex > e_star)) ? 1u : 0u;
-            const bool side = cand && !all && ex == e_star;
-            const u32 at = wave_claim(side, &s_side);
-            if (side && slab + at < b.side_cap) {
+            sidebits |= (cand && !all && ex == e_star) ? (1u << i) : 0u;
+        }
+        u32 at = wave_claim_n<M + 1>((u32)__popc(sidebits), &s_side);
+#pragma unroll Unroll<M>::value
+        for (int i = 0; i < (1 << M); ++i) {
+            if (!((sidebits >> i) & 1u)) continue;
+            if (slab + at < b.side_cap) {
                 b.side_key[slab + at] = G.rest | deposit_bits<M>((u32)i, g);
-                b.side_w[slab + at] = wb;
+                b.side_w[slab + at] = wbs[i];
             }
+            ++at;
         }
     }
     atomicAdd(&s_above, above);
@@ -876,22 +915,32 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(GateArg g, PassBufs b)
         const u64 e = base + (u64)k * STS_WG + tid;
         Group<AT, M> G;
         tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+        AT os[1 << M];
+        u32 keepbits = 0;
 #pragma unroll Unroll<M>::value
         for (int i = 0; i < (1 << M); ++i) {
-            AT o = group_out<AT, M>(g, G, i);
+            const AT o = group_out<AT, M>(g, G, i);
+            os[i] = o;
             const u64 key = G.rest | deposit_bits<M>((u32)i, g);
             const u64 wb = weight_bits(o);
             const bool keep = G.present && (M == 0 || nonzero(o)) &&
                               (all || wb > thr_w || (wb == thr_w && key <= thr_k));
-            const u32 at = wave_claim(keep, &s_out);
-            if (keep && out0 + at < b.out_cap) {
+            keepbits |= keep ? (1u << i) : 0u;
+        }
+        u32 at = wave_claim_n<M + 1>((u32)__popc(keepbits), &s_out);
+#pragma unroll Unroll<M>::value
+        for (int i = 0; i < (1 << M); ++i) {
+            if (!((keepbits >> i) & 1u)) continue;
+            if (out0 + at < b.out_cap) {
+                AT o = os[i];
                 if (rescale) {
                     o.x = (R)((double)o.x * scale);
                     o.y = (R)((double)o.y * scale);
                 }
-                b.out_keys[out0 + at] = key;
+                b.out_keys[out0 + at] = G.rest | deposit_bits<M>((u32)i, g);
                 ((AT *)b.out_amps)[out0 + at] = o;
             }
+            ++at;
         }
     }
 }

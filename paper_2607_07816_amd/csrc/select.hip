@@ -431,9 +431,31 @@ __device__ bool pick_digit(const u64 *cntp, const u64 *hip_, const u64 *lop, boo
 // ---------------------------------------------------------------------------
 // level 2 over the side buffer (many workgroups), pick by the last one
 // ---------------------------------------------------------------------------
+// LDS bins of the level-2 histogram: s_hi sums mantissa >> 20, s_lo sums
+// mantissa & (2^20 - 1) plus count << 44. A workgroup flushes them before
+// 2^19 entries have gone in, so neither field can overflow into the next.
+constexpr int SH_LOW = 20;
+constexpr u64 SH_FLUSH = 1ull << 19;
+
+__device__ __forceinline__ void side_flush(u64 *h2, u64 *s_hi, u64 *s_lo)
+{
+    for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
+        const u64 lo = s_lo[i];
+        const u64 c = lo >> 44;
+        if (c) {
+            const u128 tot = ((u128)s_hi[i] << SH_LOW) + (u128)(lo & ((1ull << 44) - 1));
+            atomicAdd(&h2[i], c);
+            atomicAdd(&h2[STS_NBIN + i], (u64)(tot >> 26));
+            atomicAdd(&h2[2 * STS_NBIN + i], (u64)tot & ((1ull << 26) - 1));
+        }
+        s_hi[i] = 0;
+        s_lo[i] = 0;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
 {
-    __shared__ u32 s_cnt[STS_NBIN];
+    constexpr int UN = 4; // entries in flight per thread
     __shared__ u64 s_hi[STS_NBIN];
     __shared__ u64 s_lo[STS_NBIN];
     __shared__ u128 s_m[256];
@@ -443,34 +465,42 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
     DevCtl *ctl = b.ctl;
     if (ctl->keep_all) return;
     for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
-        s_cnt[i] = 0;
         s_hi[i] = 0;
         s_lo[i] = 0;
     }
     __syncthreads();
     const SideChunks sc = side_chunks(b, ctl);
+    u64 since = 0;
     for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
         u64 base, count;
         chunk_range(sc, t, base, count);
-        for (u64 i = threadIdx.x; i < count; i += 256) {
-            const u64 wb = b.side_w[base + i];
-            const u64 vh = ((1ull << 52) - 1) - (wb & ((1ull << 52) - 1));
-            const u32 d = (u32)(vh >> 41);
-            const u64 mant = sts_mant(wb);
-            atomicAdd(&s_cnt[d], 1u);
-            atomicAdd(&s_hi[d], mant >> 26);
-            atomicAdd(&s_lo[d], mant & ((1ull << 26) - 1));
+        if (since + count > SH_FLUSH) { // uniform across the workgroup
+            __syncthreads();
+            side_flush(h2, s_hi, s_lo);
+            __syncthreads();
+            since = 0;
+        }
+        since += count;
+        for (u64 i0 = 0; i0 < count; i0 += UN * 256) {
+            u64 w[UN];
+#pragma unroll
+            for (int r = 0; r < UN; ++r) {
+                const u64 i = i0 + (u64)r * 256 + threadIdx.x;
+                w[r] = i < count ? b.side_w[base + i] : ~0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < UN; ++r) {
+                if (w[r] == ~0ull) continue; // past the chunk (no weight has all bits set)
+                const u64 vh = ((1ull << 52) - 1) - (w[r] & ((1ull << 52) - 1));
+                const u32 d = (u32)(vh >> 41);
+                const u64 mant = sts_mant(w[r]);
+                atomicAdd(&s_hi[d], mant >> SH_LOW);
+                atomicAdd(&s_lo[d], (mant & ((1ull << SH_LOW) - 1)) | (1ull << 44));
+            }
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
-        const u32 c = s_cnt[i];
-        if (c) {
-            atomicAdd(&h2[i], (u64)c);
-            atomicAdd(&h2[STS_NBIN + i], s_hi[i]);
-            atomicAdd(&h2[2 * STS_NBIN + i], s_lo[i]);
-        }
-    }
+    side_flush(h2, s_hi, s_lo);
     if (!sts_last_block(&ctl->done[1], &s_flag)) return;
     if (threadIdx.x == 0) {
         s_sub.cnt_before = ctl->cnt_before;
@@ -499,6 +529,7 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
 {
+    constexpr int UN = 4;
     DevCtl *ctl = b.ctl;
     if (ctl->keep_all || (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
     if (ctl->sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
@@ -506,33 +537,42 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
     const int vshift = ctl->vshift;
     const u128 vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
     const u64 lt = sts_lanemask_lt();
-    for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x)
-    for (u64 i0 = 0;; i0 += 256) {
+    for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
         u64 cbase, count;
         chunk_range(sc, t, cbase, count);
-        if (i0 >= count) break;
-        const u64 i = cbase + i0 + threadIdx.x;
-        bool take = false;
-        u64 w = 0, k = 0;
-        if (i0 + threadIdx.x < count) {
-            w = b.side_w[i];
-            k = b.side_key[i];
-            if (vshift >= 64) { // the fixed part lies in the weight half of V
-                const u64 vh = ((1ull << 52) - 1) - (w & ((1ull << 52) - 1));
-                take = (vh >> (vshift - 64)) == (u64)vpre;
-            } else {
-                take = (rank_key(w, k) >> vshift) == vpre;
+        for (u64 i0 = 0; i0 < count; i0 += UN * 256) {
+            u64 w[UN];
+#pragma unroll
+            for (int r = 0; r < UN; ++r) {
+                const u64 i = i0 + (u64)r * 256 + threadIdx.x;
+                w[r] = i < count ? b.side_w[cbase + i] : ~0ull;
             }
-        }
-        const u64 mask = __ballot(take);
-        if (!mask) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        u64 pos = 0;
-        if (sts_lane() == leader) pos = atomicAdd((unsigned long long *)&ctl->sub_n, (u64)__popcll(mask));
-        pos = __shfl(pos, leader, 64) + (u64)__popcll(mask & lt);
-        if (take && pos < b.sub_cap) {
-            b.sub_key[pos] = k;
-            b.sub_w[pos] = w;
+#pragma unroll
+            for (int r = 0; r < UN; ++r) {
+                const u64 i = cbase + i0 + (u64)r * 256 + threadIdx.x;
+                bool take = false;
+                u64 k = 0;
+                if (w[r] != ~0ull) {
+                    if (vshift >= 64) { // the fixed part lies in the weight half of V
+                        const u64 vh = ((1ull << 52) - 1) - (w[r] & ((1ull << 52) - 1));
+                        take = (vh >> (vshift - 64)) == (u64)vpre;
+                        if (take) k = b.side_key[i];
+                    } else {
+                        k = b.side_key[i];
+                        take = (rank_key(w[r], k) >> vshift) == vpre;
+                    }
+                }
+                const u64 mask = __ballot(take);
+                if (!mask) continue;
+                const int leader = __ffsll((long long)mask) - 1;
+                u64 pos = 0;
+                if (sts_lane() == leader) pos = atomicAdd((unsigned long long *)&ctl->sub_n, (u64)__popcll(mask));
+                pos = __shfl(pos, leader, 64) + (u64)__popcll(mask & lt);
+                if (take && pos < b.sub_cap) {
+                    b.sub_key[pos] = k;
+                    b.sub_w[pos] = w[r];
+                }
+            }
         }
     }
 }
@@ -706,6 +746,7 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
 {
+    constexpr int UN = 4;
     __shared__ u32 s_scratch[4];
     DevCtl *ctl = b.ctl;
     const u64 n = *b.n_in;
@@ -714,13 +755,25 @@ __global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
     if (tile >= ntiles) return;
     const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
     const int shift = ctl->side_slab_shift;
-    const u32 ns = b.t_side[tile];
+    const u64 base = tile << shift;
+    u64 ns = b.t_side[tile];
+    if (base >= b.side_cap) ns = 0;
+    else if (ns > b.side_cap - base) ns = b.side_cap - base;
     u32 c = 0;
-    for (u32 i = threadIdx.x; i < ns; i += 256) {
-        const u64 at = (tile << shift) + i;
-        if (at >= b.side_cap) break;
-        const u64 wb = b.side_w[at], key = b.side_key[at];
-        c += (wb > thr_w || (wb == thr_w && key <= thr_k)) ? 1u : 0u;
+    for (u64 i0 = 0; i0 < ns; i0 += UN * 256) {
+        u64 w[UN];
+#pragma unroll
+        for (int r = 0; r < UN; ++r) {
+            const u64 i = i0 + (u64)r * 256 + threadIdx.x;
+            w[r] = i < ns ? b.side_w[base + i] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < UN; ++r) {
+            const u64 i = i0 + (u64)r * 256 + threadIdx.x;
+            if (i >= ns) continue;
+            // ranked at or above the threshold term; the key decides only a tie
+            c += (w[r] > thr_w || (w[r] == thr_w && b.side_key[base + i] <= thr_k)) ? 1u : 0u;
+        }
     }
     u32 tot;
     (void)block_excl_scan<u32, 256>(c, s_scratch, &tot);
