@@ -60,7 +60,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=300, help="timed gate steps")
     ap.add_argument("--warmup", type=int, default=30, help="untimed gate steps before timing")
     ap.add_argument("--profile-steps", type=int, default=60, help="gate steps timed per kernel")
-    ap.add_argument("--workload", default="48q", choices=["48q", "24q"])
+    ap.add_argument("--workload", default="48q", choices=["48q", "24q", "c4"],
+                    help="48q: the 48-qubit circuit (default); 24q: a 24-qubit one; c4: 256 uneven circuits, "
+                         "batched against the plain one-at-a-time loop")
+    ap.add_argument("--batch", type=int, default=256, help="circuits of the c4 workload")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="terms in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -86,6 +89,8 @@ def main():
     from paper_2607_07816_amd import circuits as C
     from paper_2607_07816_amd._lib import State
 
+    if args.workload == "c4":
+        return bench_batch(args)
     if args.workload == "48q":
         circuit, cfg = C.workload_48q()
         prec = cfg["precision"]
@@ -209,6 +214,65 @@ def main():
             "step_algorithmic_GBps": step_bytes / (total_ms / max(nsteps, 1) / 1e3) / 1e9 if total_ms else None,
         },
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    """Many uneven circuits: the plain loop (one circuit after another on one
+    stream) against the batch runner in the configuration the autotuner picks
+    on a sample of the same batch. Every circuit's result is checked to be
+    identical between the two."""
+    import torch
+
+    from paper_2607_07816_amd import batch as B
+    from paper_2607_07816_amd import circuits as C
+
+    torch.cuda.init()
+    t = time.perf_counter()
+    ws = C.batch_workload(args.batch, 4)
+    items = [(c, cfg["K"], cfg["p"]) for c, cfg in ws]
+    log(f"{len(items)} circuits generated in {time.perf_counter() - t:.1f}s "
+        f"({sum(len(c.gates) for c, _, _ in items)} gates)")
+    packed = B.pack(items)
+    # warm-up: code objects, allocator
+    B.run_batch(items[:8], "c64", 4, 0)
+    plain, t_plain = B.run_batch(items, "c64", 1, 0, packed=packed)
+    upd = sum(r["term_updates"] for r in plain)
+    log(f"plain loop: {t_plain:.2f}s, {upd} updates, {upd / t_plain:.3e} updates/s")
+    t = time.perf_counter()
+    choice, timings = B.autotune(items, "c64")
+    t_tune = time.perf_counter() - t
+    log(f"autotune {t_tune:.1f}s: " + ", ".join(f"s{k[0]}/g{k[1]} {v:.2f}s" for k, v in sorted(timings.items())))
+    res, t_batch = B.run_batch(items, "c64", choice[0], choice[1], packed=packed)
+    same = all(all(a[f] == b[f] for f in ("peak_key", "peak_prob", "n_terms", "term_updates", "log10_cum_kept"))
+               for a, b in zip(plain, res))
+    log(f"batch s{choice[0]}/g{choice[1]}: {t_batch:.2f}s, {upd / t_batch:.3e} updates/s, "
+        f"{t_plain / t_batch:.2f}x the plain loop; results identical: {same}")
+    if not same:
+        raise SystemExit("batched results differ from the plain loop")
+    line = {
+        "metric": "gate-term updates/s",
+        "value": upd / t_batch,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": sum(r["gate_steps"] for r in res),
+        "warmup": 0,
+        "ms_per_step": t_batch / max(sum(r["gate_steps"] for r in res), 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"batch{len(items)}_uneven_n16-40_K2^12-2^20_c64", "circuits": len(items),
+                   "streams": choice[0], "graph_steps": choice[1]},
+        "plain_loop": {"value": upd / t_plain, "seconds": t_plain},
+        "batch_seconds": t_batch,
+        "speedup_vs_plain": t_plain / t_batch,
+        "autotune": {"seconds": t_tune, "sample": "every 4th circuit",
+                     "timings": {f"s{k[0]}/g{k[1]}": v for k, v in sorted(timings.items())}},
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

@@ -85,7 +85,8 @@ sts_status sts_required_bytes(uint64_t cap_terms, int precision, size_t *bytes);
 
 /*
  * Create a state of n_qubits (1..64) in the ground state (one term, key 0,
- * amplitude 1). max_terms = K of top-k truncation (0 = off); mass = p of
+ * amplitude 1). max_terms = K of top-k truncation (0 = off; a K above
+ * 2^n_qubits never cuts and is taken as 2^n_qubits); mass = p of
  * p-mass truncation (off unless 0 < p < 1). Both may be given: p-mass first,
  * then top-k (Sec. III). hip_stream: a hipStream_t, NULL = the null stream.
  * arena/arena_bytes: device memory to carve every buffer from (NULL/0 = the
@@ -165,6 +166,63 @@ sts_status sts_profile(sts_ctx *ctx, int enable);
 /* Total time (ms) and number of launches of one kernel kind since timing was
  * turned on (or last reset with reset = 1). Synchronises. */
 sts_status sts_kernel_time(sts_ctx *ctx, int kind, int reset, double *total_ms, uint64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent circuits.
+ *
+ * At small k the cost of a gate step is a fixed overhead rather than work
+ * proportional to k (Sec. VI.B), so running one circuit at a time leaves the
+ * GPU mostly idle. sts_batch_run keeps several circuits in flight at once.
+ * Each circuit runs through its own context exactly as it would alone
+ * (sts_init, then sts_apply_gate / sts_truncate per gate, then sts_peak), so
+ * its results do not depend on the rest of the batch.
+ * ------------------------------------------------------------------------ */
+
+/* One circuit: n_gates gates in order, flattened. Gate i acts on gate_m[i]
+ * (1..5) qubits, listed next in gate_qubits, with the next 2*4^m doubles of
+ * gate_U as its matrix (layout of sts_apply_gate); truncate_after[i] != 0
+ * truncates right after it. max_terms and mass as in sts_init. The arrays
+ * are the caller's and are read during the call. */
+typedef struct {
+    int n_qubits;
+    uint64_t max_terms;
+    double mass;
+    uint64_t n_gates;
+    const int *gate_m;
+    const int *gate_qubits;
+    const double *gate_U;
+    const uint8_t *truncate_after;
+} sts_circuit;
+
+typedef struct {
+    int precision;   /* STS_C128 or STS_C64, for every circuit                 */
+    int n_streams;   /* circuits in flight, 1..64: each has a host thread, a   */
+                     /* HIP stream and a device arena of its own               */
+    int graph_steps; /* 0: plain launches; g > 0: record up to g consecutive    */
+                     /* truncated gates of <= 3 qubits into one HIP graph and   */
+                     /* launch that                                            */
+} sts_batch_config;
+
+typedef struct {
+    sts_status status;      /* STS_OK, or the first error of this circuit     */
+    uint64_t peak_key;      /* sts_peak at the end                            */
+    double peak_prob;
+    uint64_t n_terms;       /* terms held at the end                          */
+    uint64_t gate_steps;    /* sts_counters at the end                        */
+    uint64_t term_updates;
+    double log10_cum_kept;  /* sts_stats at the end                           */
+    double seconds;         /* host wall time from its sts_init to its result */
+} sts_circuit_result;
+
+/* Run n circuits on the current device. The library allocates one arena per
+ * stream (sized for the largest circuit: max(K, 1024) terms, times 2^m if an
+ * untruncated gate of m qubits occurs) and frees it before returning. The
+ * longest circuits (gates x min(K, 2^n)) start first. results[n] receives
+ * one entry per circuit, in input order. Returns STS_E_ARG for bad arguments
+ * (nothing runs), the first error of any circuit otherwise, or STS_OK.
+ * Synchronises. */
+sts_status sts_batch_run(int n, const sts_circuit *circuits, const sts_batch_config *cfg,
+                         sts_circuit_result *results);
 
 /* Release the context and the device memory it allocated. NULL is a no-op. */
 void sts_free(sts_ctx *ctx);

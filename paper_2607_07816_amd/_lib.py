@@ -23,11 +23,30 @@ STS_C128, STS_C64 = 0, 1
 EXPORTS = (
     "sts_required_bytes", "sts_init", "sts_apply_gate", "sts_truncate", "sts_peak",
     "sts_num_terms", "sts_read_terms", "sts_load_terms", "sts_stats", "sts_counters",
-    "sts_profile", "sts_kernel_time", "sts_free", "sts_strerror",
+    "sts_profile", "sts_kernel_time", "sts_free", "sts_strerror", "sts_batch_run",
 )
 
 KERNEL_KINDS = ("radix_hist", "radix_scan", "radix_pass", "group_hist", "pick1", "group_extract",
                 "side_hist", "final", "group_emit", "side_extract", "tile_kept", "tile_scan")
+
+
+class Circuit(ctypes.Structure):
+    """sts_circuit: one circuit of a batch (flattened gate arrays)."""
+    _fields_ = [("n_qubits", ctypes.c_int), ("max_terms", ctypes.c_uint64), ("mass", ctypes.c_double),
+                ("n_gates", ctypes.c_uint64), ("gate_m", ctypes.c_void_p), ("gate_qubits", ctypes.c_void_p),
+                ("gate_U", ctypes.c_void_p), ("truncate_after", ctypes.c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    """sts_batch_config."""
+    _fields_ = [("precision", ctypes.c_int), ("n_streams", ctypes.c_int), ("graph_steps", ctypes.c_int)]
+
+
+class CircuitResult(ctypes.Structure):
+    """sts_circuit_result."""
+    _fields_ = [("status", ctypes.c_int), ("peak_key", ctypes.c_uint64), ("peak_prob", ctypes.c_double),
+                ("n_terms", ctypes.c_uint64), ("gate_steps", ctypes.c_uint64), ("term_updates", ctypes.c_uint64),
+                ("log10_cum_kept", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class StsError(RuntimeError):
@@ -50,6 +69,10 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run paper_2607_07816_amd/build.py (hipcc, gfx950)")
+    # torch first: its HIP runtime has the same soname as the one libsts
+    # links, so loading torch's makes libsts bind to it. Loaded the other way
+    # round the process would hold two HIP runtimes and torch's would fail.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, dbl = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_double
     L.sts_required_bytes.argtypes = [u64, i32, ctypes.POINTER(ctypes.c_size_t)]
@@ -66,6 +89,8 @@ def load() -> ctypes.CDLL:
     L.sts_kernel_time.argtypes = [vp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(u64)]
     L.sts_free.argtypes = [vp]
     L.sts_free.restype = None
+    L.sts_batch_run.argtypes = [i32, ctypes.POINTER(Circuit), ctypes.POINTER(BatchConfig),
+                                ctypes.POINTER(CircuitResult)]
     L.sts_strerror.argtypes = [i32]
     L.sts_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:

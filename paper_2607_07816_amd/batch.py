@@ -1,0 +1,79 @@
+"""Batches of independent circuits on one GPU (sts_batch_run) and a small
+autotuner for the batch runner's launch configuration.
+
+A batch item is (circuit, K, p). Every circuit runs through its own context,
+exactly as it would alone; the batch only decides how many run at once
+(`streams`) and whether runs of truncated gates are launched as HIP graphs
+(`graph_steps`).
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+
+
+class _Packed:
+    """A circuit flattened into the arrays sts_circuit points at (kept alive here)."""
+
+    def __init__(self, circuit, K: int, p: float):
+        self.m = np.ascontiguousarray([len(qs) for qs, _ in circuit.gates], dtype=np.int32)
+        self.q = np.ascontiguousarray([q for qs, _ in circuit.gates for q in qs], dtype=np.int32)
+        self.u = np.ascontiguousarray(np.concatenate(
+            [np.ascontiguousarray(u, dtype=np.complex128).reshape(-1).view(np.float64) for _, u in circuit.gates])
+            if circuit.gates else np.zeros(0), dtype=np.float64)
+        self.t = np.ascontiguousarray(circuit.truncate_after, dtype=np.uint8)
+        self.c = _lib.Circuit(int(circuit.n), int(K), float(p), len(circuit.gates), self.m.ctypes.data,
+                              self.q.ctypes.data, self.u.ctypes.data, self.t.ctypes.data)
+
+
+def pack(items: Sequence[Tuple[object, int, float]]) -> List[_Packed]:
+    return [_Packed(c, K, p) for c, K, p in items]
+
+
+def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, packed=None) -> Tuple[list, float]:
+    """Run every (circuit, K, p) of `items`; returns (per-circuit result
+    dicts in input order, wall seconds of the whole batch)."""
+    L = _lib.load()
+    packed = packed if packed is not None else pack(items)
+    n = len(packed)
+    arr = (_lib.Circuit * max(n, 1))(*[pk.c for pk in packed])
+    res = (_lib.CircuitResult * max(n, 1))()
+    cfg = _lib.BatchConfig(_lib._prec(precision), int(streams), int(graph_steps))
+    t0 = time.perf_counter()
+    rc = L.sts_batch_run(n, arr, ctypes.byref(cfg), res)
+    dt = time.perf_counter() - t0
+    _lib._check(rc, "sts_batch_run")
+    out = []
+    for i in range(n):
+        r = res[i]
+        out.append(dict(status=r.status, peak_key=int(r.peak_key), peak_prob=r.peak_prob, n_terms=int(r.n_terms),
+                        gate_steps=int(r.gate_steps), term_updates=int(r.term_updates),
+                        log10_cum_kept=r.log10_cum_kept, seconds=r.seconds))
+    return out, dt
+
+
+DEFAULT_CANDIDATES = tuple((s, g) for s in (4, 8, 16, 32, 48) for g in (0, 16))
+
+
+def autotune(items, precision="c64", sample: Optional[Sequence[int]] = None,
+             candidates: Iterable[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 1):
+    """Time each (streams, graph_steps) candidate on a sample of the batch
+    and return (best config, {config: seconds}). The sample keeps the batch's
+    mix: by default every fourth circuit."""
+    idx = list(sample) if sample is not None else list(range(0, len(items), 4))
+    sub = [items[i] for i in idx]
+    packed = pack(sub)
+    timings = {}
+    for cfg in candidates:
+        best = None
+        for _ in range(repeats):
+            _, dt = run_batch(sub, precision, cfg[0], cfg[1], packed=packed)
+            best = dt if best is None else min(best, dt)
+        timings[cfg] = best
+    choice = min(timings, key=timings.get)
+    return choice, timings

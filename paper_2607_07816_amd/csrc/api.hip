@@ -377,6 +377,8 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     if (!(mass == mass)) return STS_E_ARG; // NaN
     if (arena && arena_bytes == 0) return STS_E_ARG;
     if (cap_terms > (1ull << 36)) return STS_E_ARG;
+    // n qubits have at most 2^n basis keys, so a larger K never cuts
+    if (n_qubits < 64) max_terms = std::min<u64>(max_terms, 1ull << n_qubits);
     u64 cap = cap_terms;
     if (arena) {
         if (cap == 0) {

@@ -1,0 +1,206 @@
+// batch.hip - many independent circuits on one GPU.
+//
+// At small k a gate step is a fixed cost of a dozen short kernel launches
+// (the GPU overhead visible at low k in Sec. VI.B), so one circuit at a time
+// leaves most of the device idle. The batch runner keeps several circuits in
+// flight: each worker is a host thread with its own HIP stream and its own
+// device arena, and runs whole circuits through an ordinary context carved
+// from that arena, so every circuit computes exactly what it computes alone.
+// Circuits are handed out longest first (work ~ gates x min(K, 2^n)).
+// Optionally, runs of consecutive truncated gates (m <= 3) are captured into a
+// HIP graph and launched as one, which replaces a dozen launch calls per gate
+// by one graph launch per chunk.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "sts.h"
+#include "kernels.h"
+
+namespace {
+
+struct BatchJob {
+    int idx;
+    double work;
+};
+
+bool circuit_valid(const sts_circuit &c)
+{
+    if (c.n_qubits < 1 || c.n_qubits > 64) return false;
+    if (c.n_gates && (!c.gate_m || !c.gate_qubits || !c.gate_U || !c.truncate_after)) return false;
+    for (u64 i = 0; i < c.n_gates; ++i)
+        if (c.gate_m[i] < 1 || c.gate_m[i] > STS_MAXM) return false;
+    return true;
+}
+
+// terms a circuit's context must hold: K for truncated steps, and room for an
+// untruncated gate's 2^m x K candidates
+u64 circuit_cap(const sts_circuit &c)
+{
+    const u64 full = c.n_qubits >= 40 ? (1ull << 40) : (1ull << c.n_qubits);
+    u64 k = c.max_terms ? std::min<u64>(c.max_terms, full) : full;
+    int m_free = 0;
+    for (u64 i = 0; i < c.n_gates; ++i)
+        if (!c.truncate_after[i]) m_free = std::max(m_free, c.gate_m[i]);
+    u64 cap = k << m_free;
+    cap = std::min<u64>(std::max<u64>(cap, 1024), 1ull << 36);
+    return cap;
+}
+
+double circuit_work(const sts_circuit &c)
+{
+    const double full = c.n_qubits >= 40 ? 1e12 : (double)(1ull << c.n_qubits);
+    const double k = c.max_terms ? std::min((double)c.max_terms, full) : full;
+    return (double)c.n_gates * k;
+}
+
+struct Graphs {
+    std::vector<hipGraph_t> g;
+    std::vector<hipGraphExec_t> x;
+    void clear()
+    {
+        for (auto e : x) (void)hipGraphExecDestroy(e);
+        for (auto h : g) (void)hipGraphDestroy(h);
+        x.clear();
+        g.clear();
+    }
+};
+
+// one circuit start to finish on an existing stream and arena
+void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, void *arena, size_t arena_bytes,
+             sts_circuit_result *r)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    std::memset(r, 0, sizeof(*r));
+    sts_ctx *ctx = nullptr;
+    sts_status st = sts_init(&ctx, c.n_qubits, c.max_terms, c.mass, prec, s, arena, arena_bytes, circuit_cap(c));
+    Graphs graphs;
+    u64 qo = 0, uo = 0;
+    u64 i = 0;
+    bool prev_truncated = true;
+    while (st == STS_OK && i < c.n_gates) {
+        const int m = c.gate_m[i];
+        const bool capturable = graph_steps > 0 && c.max_terms > 0 && m <= 3 && c.truncate_after[i] &&
+                                prev_truncated;
+        if (!capturable) {
+            st = sts_apply_gate(ctx, m, c.gate_qubits + qo, c.gate_U + uo);
+            if (st == STS_OK && c.truncate_after[i]) st = sts_truncate(ctx);
+            prev_truncated = c.truncate_after[i] != 0;
+            qo += (u64)m;
+            uo += 2ull << (2 * m);
+            ++i;
+            continue;
+        }
+        // a chunk of consecutive truncated gates of up to 3 qubits: no call in
+        // it synchronises, so the whole chunk records into one graph
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            st = STS_E_HIP;
+            break;
+        }
+        int k = 0;
+        while (st == STS_OK && i < c.n_gates && k < graph_steps && c.gate_m[i] <= 3 && c.truncate_after[i]) {
+            const int mi = c.gate_m[i];
+            st = sts_apply_gate(ctx, mi, c.gate_qubits + qo, c.gate_U + uo);
+            if (st == STS_OK) st = sts_truncate(ctx);
+            qo += (u64)mi;
+            uo += 2ull << (2 * mi);
+            ++i;
+            ++k;
+        }
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(s, &gr);
+        if (st != STS_OK || e != hipSuccess || !gr) {
+            if (gr) (void)hipGraphDestroy(gr);
+            if (st == STS_OK) st = STS_E_HIP;
+            break;
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ex, s);
+        graphs.g.push_back(gr);
+        if (ex) graphs.x.push_back(ex);
+        if (e != hipSuccess) st = STS_E_HIP;
+        prev_truncated = true;
+    }
+    if (st == STS_OK) st = sts_peak(ctx, &r->peak_key, &r->peak_prob); // synchronises
+    if (st == STS_OK) st = sts_num_terms(ctx, &r->n_terms);
+    if (st == STS_OK) st = sts_counters(ctx, &r->gate_steps, &r->term_updates, nullptr);
+    if (st == STS_OK) st = sts_stats(ctx, nullptr, nullptr, &r->log10_cum_kept, nullptr);
+    if (ctx) sts_free(ctx); // waits for the stream
+    graphs.clear();
+    r->status = st;
+    r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+} // namespace
+
+extern "C" sts_status sts_batch_run(int n, const sts_circuit *circuits, const sts_batch_config *cfg,
+                                    sts_circuit_result *results)
+{
+    if (n < 0 || (n > 0 && (!circuits || !results)) || !cfg) return STS_E_ARG;
+    if (cfg->precision != STS_C128 && cfg->precision != STS_C64) return STS_E_ARG;
+    if (cfg->n_streams < 1 || cfg->n_streams > 64 || cfg->graph_steps < 0) return STS_E_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!circuit_valid(circuits[i])) return STS_E_ARG;
+    if (n == 0) return STS_OK;
+    for (int i = 0; i < n; ++i) {
+        std::memset(&results[i], 0, sizeof(results[i]));
+        results[i].status = STS_E_STATE; // until a worker has run it
+    }
+
+    std::vector<BatchJob> jobs(n);
+    u64 cap_max = 1024;
+    for (int i = 0; i < n; ++i) {
+        jobs[i].idx = i;
+        jobs[i].work = circuit_work(circuits[i]);
+        cap_max = std::max(cap_max, circuit_cap(circuits[i]));
+    }
+    std::stable_sort(jobs.begin(), jobs.end(), [](const BatchJob &a, const BatchJob &b) { return a.work > b.work; });
+    size_t bytes = 0;
+    sts_status st = sts_required_bytes(cap_max, cfg->precision, &bytes);
+    if (st != STS_OK) return st;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return STS_E_HIP;
+
+    const int workers = std::min(cfg->n_streams, n);
+    std::atomic<int> next{0};
+    std::atomic<int> setup_err{0};
+    auto worker = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) {
+            setup_err = STS_E_HIP;
+            return;
+        }
+        hipStream_t s = nullptr;
+        void *arena = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            setup_err = STS_E_HIP;
+            return;
+        }
+        const hipError_t e = hipMalloc(&arena, bytes);
+        if (e != hipSuccess) {
+            setup_err = e == hipErrorOutOfMemory ? STS_E_NOMEM : STS_E_HIP;
+            (void)hipStreamDestroy(s);
+            return;
+        }
+        for (int j = next.fetch_add(1); j < n; j = next.fetch_add(1)) {
+            const int idx = jobs[j].idx;
+            run_one(circuits[idx], cfg->precision, cfg->graph_steps, s, arena, bytes, &results[idx]);
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(arena);
+        (void)hipStreamDestroy(s);
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(workers);
+    for (int w = 0; w < workers; ++w) pool.emplace_back(worker);
+    for (auto &t : pool) t.join();
+    for (int i = 0; i < n; ++i)
+        if (results[i].status == STS_E_STATE && setup_err.load()) return (sts_status)setup_err.load();
+    for (int i = 0; i < n; ++i)
+        if (results[i].status != STS_OK) return results[i].status;
+    return STS_OK;
+}

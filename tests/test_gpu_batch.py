@@ -1,0 +1,75 @@
+"""Batches of circuits (sts_batch_run) against the same circuits run alone.
+
+Each circuit of a batch runs through its own context, so whatever the
+number of circuits in flight or the use of HIP graphs, its results must be
+bit for bit those of the plain per-circuit loop; in FP64 they must also
+match the CPU oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import dict_oracle as O
+from paper_2607_07816_amd import batch as B
+from paper_2607_07816_amd import circuits as C
+from paper_2607_07816_amd.run import run_circuit
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("peak_key", "peak_prob", "n_terms", "gate_steps", "term_updates", "log10_cum_kept")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_items(num=12, seed=11):
+    ws = C.batch_workload(num, seed, n_range=(8, 14), depth_range=(2, 5), logk_range=(5, 9))
+    return [(c, cfg["K"], 0.0) for c, cfg in ws]
+
+
+def alone(c, K, p, prec):
+    st = run_circuit(c, K=K, p=p, precision=prec, capacity=max(2 * K, 1024))
+    key, prob = st.peak()
+    out = dict(peak_key=key, peak_prob=prob, n_terms=st.num_terms())
+    cnt = st.counters()
+    out.update(gate_steps=cnt["gate_steps"], term_updates=cnt["term_updates"],
+               log10_cum_kept=st.stats()["log10_cum_kept"])
+    st.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("streams,graph", [(1, 0), (4, 0), (4, 8), (3, 1)])
+def test_batch_equals_alone(prec, streams, graph):
+    items = small_items()
+    say(f"[batch] {len(items)} circuits, {prec}, streams={streams}, graph_steps={graph}")
+    res, dt = B.run_batch(items, prec, streams, graph)
+    for (c, K, p), r in zip(items, res):
+        ref = alone(c, K, p, prec)
+        assert r["status"] == 0
+        for f in FIELDS:
+            assert r[f] == ref[f], (c.name, f, r[f], ref[f])
+
+
+def test_batch_fp64_matches_oracle():
+    items = small_items(8, seed=12)
+    res, _ = B.run_batch(items, "c128", 4, 8)
+    for (c, K, p), r in zip(items, res):
+        state = O.run_circuit(c.gates, c.truncate_after, K, p)
+        key, prob = O.peak(state)
+        say(f"[batch] {c.name}: K={K} terms {r['n_terms']} oracle {len(state)} peak {r['peak_key']:#x}")
+        assert r["n_terms"] == len(state)
+        assert r["peak_key"] == key
+        assert abs(r["peak_prob"] - prob) <= 1e-12
+
+
+def test_batch_uneven_sizes_and_order():
+    # a mix of sizes; results come back in input order whatever ran first
+    items = small_items(6, seed=13) + [(C.workload_small()[0], 1024, 0.0)]
+    res, _ = B.run_batch(items[::-1], "c64", 2, 4)
+    for (c, K, p), r in zip(items[::-1], res):
+        ref = alone(c, K, p, "c64")
+        assert r["peak_key"] == ref["peak_key"] and r["n_terms"] == ref["n_terms"]

@@ -60,8 +60,8 @@ def test_init_rejects_bad_arguments_before_any_device_work(lib):
     for n, prec in ((0, 0), (65, 0), (10, 7)):
         rc = lib.sts_init(ctypes.byref(ctx), n, 16, 0.0, prec, None, None, 0, 0)
         assert rc == -1 and not ctx.value
-    # K larger than the capacity asked for
-    rc = lib.sts_init(ctypes.byref(ctx), 10, 1 << 20, 0.0, 0, None, None, 0, 1024)
+    # K larger than the capacity asked for (and below 2^n, so it can cut)
+    rc = lib.sts_init(ctypes.byref(ctx), 30, 1 << 20, 0.0, 0, None, None, 0, 1024)
     assert rc == -3 and not ctx.value
 
 
@@ -71,3 +71,25 @@ def test_calls_on_null_context_fail_cleanly(lib):
     assert lib.sts_apply_gate(None, 1, q, u) == -1
     assert lib.sts_truncate(None) == -1
     lib.sts_free(None)
+
+
+def test_batch_rejects_bad_config_without_running(lib):
+    import ctypes
+
+    from paper_2607_07816_amd import _lib
+    res = (_lib.CircuitResult * 1)()
+    circ = (_lib.Circuit * 1)()
+    m = (ctypes.c_int * 1)(2)
+    q = (ctypes.c_int * 2)(0, 1)
+    u = (ctypes.c_double * 32)()
+    t = (ctypes.c_uint8 * 1)(1)
+    circ[0] = _lib.Circuit(4, 16, 0.0, 1, ctypes.addressof(m), ctypes.addressof(q), ctypes.addressof(u),
+                           ctypes.addressof(t))
+    for cfg in (_lib.BatchConfig(_lib.STS_C64, 0, 0), _lib.BatchConfig(_lib.STS_C64, 65, 0),
+                _lib.BatchConfig(7, 2, 0), _lib.BatchConfig(_lib.STS_C64, 2, -1)):
+        assert lib.sts_batch_run(1, circ, ctypes.byref(cfg), res) == _lib.STS_E_ARG
+    # a gate of 6 qubits, or 0 qubits, is refused before anything runs
+    for bad in (6, 0):
+        m[0] = bad
+        assert lib.sts_batch_run(1, circ, ctypes.byref(_lib.BatchConfig(_lib.STS_C64, 2, 0)), res) == _lib.STS_E_ARG
+    assert lib.sts_batch_run(0, None, ctypes.byref(_lib.BatchConfig(_lib.STS_C64, 2, 0)), None) == _lib.STS_OK
