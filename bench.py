@@ -60,9 +60,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=300, help="timed gate steps")
     ap.add_argument("--warmup", type=int, default=30, help="untimed gate steps before timing")
     ap.add_argument("--profile-steps", type=int, default=60, help="gate steps timed per kernel")
-    ap.add_argument("--workload", default="48q", choices=["48q", "24q", "c4"],
+    ap.add_argument("--workload", default="48q", choices=["48q", "24q", "c4", "c5"],
                     help="48q: the 48-qubit circuit (default); 24q: a 24-qubit one; c4: 256 uneven circuits, "
-                         "batched against the plain one-at-a-time loop")
+                         "batched against the plain one-at-a-time loop; c5: Poisson arrivals served with "
+                         "continuous batching against the plain loop")
+    ap.add_argument("--requests", type=int, default=48, help="requests of the c5 workload")
+    ap.add_argument("--load", type=float, default=0.7, help="c5 offered load, as a fraction of served capacity")
     ap.add_argument("--batch", type=int, default=256, help="circuits of the c4 workload")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="terms in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,6 +94,8 @@ def main():
 
     if args.workload == "c4":
         return bench_batch(args)
+    if args.workload == "c5":
+        return bench_serve(args)
     if args.workload == "48q":
         circuit, cfg = C.workload_48q()
         prec = cfg["precision"]
@@ -271,6 +276,104 @@ def bench_batch(args):
         "speedup_vs_plain": t_plain / t_batch,
         "autotune": {"seconds": t_tune, "sample": "every 4th circuit",
                      "timings": {f"s{k[0]}/g{k[1]}": v for k, v in sorted(timings.items())}},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def serve_run(items, arrivals, streams, active, turn, hbm):
+    """Submit items at the given arrival times (seconds from start) to a
+    fresh server; returns (results in item order, makespan seconds)."""
+    import threading
+
+    from paper_2607_07816_amd.serve import Server
+
+    with Server("c64", streams, active, turn, hbm_bytes=hbm) as srv:
+        tickets = [None] * len(items)
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (c, K, p) in enumerate(items):
+                d = arrivals[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(c, K, p)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        span = time.perf_counter() - t0
+    return res, span
+
+
+def bench_serve(args):
+    """Poisson arrivals of uneven requests, served with continuous batching,
+    against the plain loop (one request at a time, in arrival order) fed the
+    same arrivals."""
+    import numpy as np
+    import torch
+
+    from paper_2607_07816_amd import circuits as C
+
+    torch.cuda.init()
+    t = time.perf_counter()
+    ws = C.serving_workload(args.requests, 5)
+    items = [(c, cfg["K"], cfg["p"]) for c, cfg in ws]
+    log(f"{len(items)} requests generated in {time.perf_counter() - t:.1f}s "
+        f"({sum(len(c.gates) for c, _, _ in items)} gates)")
+    free, _ = torch.cuda.mem_get_info()
+    hbm = int(min(free // 2, 96 << 30))
+    cfg = (16, 2, 8)
+    serve_run(items[:4], [0.0] * 4, 4, 2, 8, 8 << 30)  # warm-up
+    res0, span0 = serve_run(items, [0.0] * len(items), *cfg, hbm)
+    cap_rps = len(items) / span0
+    upd = sum(r["term_updates"] for r in res0)
+    log(f"capacity probe (all at t=0): {span0:.2f}s, {cap_rps:.2f} requests/s, {upd / span0:.3e} updates/s")
+    lam = args.load * cap_rps
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(items))).tolist()
+
+    def summary(res, span):
+        lat = np.array([r["latency_seconds"] for r in res])
+        return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "mean_s": float(lat.mean()), "makespan_s": span,
+                "throughput_updates_per_s": sum(r["term_updates"] for r in res) / span,
+                "throughput_requests_per_s": len(res) / span}
+
+    res_s, span_s = serve_run(items, arrivals, *cfg, hbm)
+    served = summary(res_s, span_s)
+    log(f"served at {lam:.2f} req/s: p50 {served['p50_s']:.3f}s p99 {served['p99_s']:.3f}s, "
+        f"{served['throughput_updates_per_s']:.3e} updates/s")
+    res_p, span_p = serve_run(items, arrivals, 1, 1, 1 << 30, hbm)
+    plain = summary(res_p, span_p)
+    log(f"plain loop at {lam:.2f} req/s: p50 {plain['p50_s']:.3f}s p99 {plain['p99_s']:.3f}s, "
+        f"{plain['throughput_updates_per_s']:.3e} updates/s")
+    same = all(all(a[f] == b[f] for f in ("peak_key", "peak_prob", "n_terms", "term_updates", "log10_cum_kept"))
+               for a, b in zip(res_s, res_p))
+    log(f"served results identical to the plain loop: {same}")
+    if not same:
+        raise SystemExit("served results differ from the plain loop")
+    line = {
+        "metric": "gate-term updates/s",
+        "value": served["throughput_updates_per_s"],
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": sum(r["gate_steps"] for r in res_s),
+        "warmup": 0,
+        "ms_per_step": span_s / max(sum(r["gate_steps"] for r in res_s), 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"serve{len(items)}_poisson_n20-64_K2^14-2^22_topk-or-p0.99_c64",
+                   "requests": len(items), "offered_rps": lam, "load_fraction": args.load,
+                   "streams": cfg[0], "max_active": cfg[1], "gates_per_turn": cfg[2], "hbm_budget_bytes": hbm},
+        "served": served,
+        "plain_loop": plain,
+        "capacity_probe": {"makespan_s": span0, "requests_per_s": cap_rps},
         "roofline": None,
         "cpu_baseline": None,
     }

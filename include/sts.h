@@ -212,6 +212,9 @@ typedef struct {
     uint64_t term_updates;
     double log10_cum_kept;  /* sts_stats at the end                           */
     double seconds;         /* host wall time from its sts_init to its result */
+    double queue_seconds;   /* server: from submission to admission (else 0)  */
+    double latency_seconds; /* server: from submission to result (else        */
+                            /* equal to seconds)                              */
 } sts_circuit_result;
 
 /* Run n circuits on the current device. The library allocates one arena per
@@ -223,6 +226,53 @@ typedef struct {
  * Synchronises. */
 sts_status sts_batch_run(int n, const sts_circuit *circuits, const sts_batch_config *cfg,
                          sts_circuit_result *results);
+
+/* ------------------------------------------------------------------------
+ * A resident server with continuous batching.
+ *
+ * Requests are circuits submitted at any time from any thread. Worker
+ * threads (one HIP stream each) admit queued requests in submission order
+ * whenever a block for the request's context fits in the server's device
+ * memory budget, keep up to max_active requests each, and advance them in
+ * turn by gates_per_turn gates, so a request that arrives while long ones
+ * run starts at the next turn. Each request runs through its own context
+ * exactly as alone (sts_init, gates, sts_peak), so its result does not
+ * depend on what else is being served.
+ * ------------------------------------------------------------------------ */
+typedef struct sts_server sts_server;
+
+typedef struct {
+    int precision;       /* STS_C128 or STS_C64, for every request            */
+    int n_streams;       /* worker threads / HIP streams, 1..64               */
+    int max_active;      /* requests a worker interleaves, 1..64              */
+    int gates_per_turn;  /* gates a request advances per turn, >= 1           */
+    uint64_t hbm_bytes;  /* device memory for request contexts, allocated at  */
+                         /* creation; 0 = half of the free device memory      */
+} sts_server_config;
+
+/* Start a server on the current device (allocates its memory budget and
+ * starts its workers). */
+sts_status sts_server_create(sts_server **out, const sts_server_config *cfg);
+
+/* Queue a circuit (layout of sts_circuit; its arrays are copied before the
+ * call returns) and return its ticket. STS_E_CAPACITY if the request's
+ * context could never fit in the budget; STS_E_STATE once the server is
+ * being destroyed. Thread-safe. */
+sts_status sts_server_submit(sts_server *s, const sts_circuit *c, uint64_t *ticket);
+
+/* Wait for a request to finish and take its result (queue_seconds and
+ * latency_seconds measured from its submission). Each ticket can be taken
+ * once; STS_E_ARG for an unknown ticket. Thread-safe. */
+sts_status sts_server_wait(sts_server *s, uint64_t ticket, sts_circuit_result *out);
+
+/* Requests queued, running and finished so far, and device bytes held by
+ * running requests. Any pointer may be NULL. Thread-safe. */
+sts_status sts_server_stats(sts_server *s, uint64_t *queued, uint64_t *active, uint64_t *done,
+                            uint64_t *bytes_in_use);
+
+/* Finish every submitted request, stop the workers and free the budget.
+ * Results not taken are dropped. NULL is a no-op. */
+void sts_server_destroy(sts_server *s);
 
 /* Release the context and the device memory it allocated. NULL is a no-op. */
 void sts_free(sts_ctx *ctx);

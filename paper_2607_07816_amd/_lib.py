@@ -24,6 +24,7 @@ EXPORTS = (
     "sts_required_bytes", "sts_init", "sts_apply_gate", "sts_truncate", "sts_peak",
     "sts_num_terms", "sts_read_terms", "sts_load_terms", "sts_stats", "sts_counters",
     "sts_profile", "sts_kernel_time", "sts_free", "sts_strerror", "sts_batch_run",
+    "sts_server_create", "sts_server_submit", "sts_server_wait", "sts_server_stats", "sts_server_destroy",
 )
 
 KERNEL_KINDS = ("radix_hist", "radix_scan", "radix_pass", "group_hist", "pick1", "group_extract",
@@ -46,7 +47,14 @@ class CircuitResult(ctypes.Structure):
     """sts_circuit_result."""
     _fields_ = [("status", ctypes.c_int), ("peak_key", ctypes.c_uint64), ("peak_prob", ctypes.c_double),
                 ("n_terms", ctypes.c_uint64), ("gate_steps", ctypes.c_uint64), ("term_updates", ctypes.c_uint64),
-                ("log10_cum_kept", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("log10_cum_kept", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("queue_seconds", ctypes.c_double), ("latency_seconds", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    """sts_server_config."""
+    _fields_ = [("precision", ctypes.c_int), ("n_streams", ctypes.c_int), ("max_active", ctypes.c_int),
+                ("gates_per_turn", ctypes.c_int), ("hbm_bytes", ctypes.c_uint64)]
 
 
 class StsError(RuntimeError):
@@ -91,10 +99,16 @@ def load() -> ctypes.CDLL:
     L.sts_free.restype = None
     L.sts_batch_run.argtypes = [i32, ctypes.POINTER(Circuit), ctypes.POINTER(BatchConfig),
                                 ctypes.POINTER(CircuitResult)]
+    L.sts_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ServerConfig)]
+    L.sts_server_submit.argtypes = [vp, ctypes.POINTER(Circuit), ctypes.POINTER(u64)]
+    L.sts_server_wait.argtypes = [vp, u64, ctypes.POINTER(CircuitResult)]
+    L.sts_server_stats.argtypes = [vp] + [ctypes.POINTER(u64)] * 4
+    L.sts_server_destroy.argtypes = [vp]
+    L.sts_server_destroy.restype = None
     L.sts_strerror.argtypes = [i32]
     L.sts_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("sts_free", "sts_strerror"):
+        if name not in ("sts_free", "sts_strerror", "sts_server_destroy"):
             getattr(L, name).restype = i32
     _lib = L
     return L

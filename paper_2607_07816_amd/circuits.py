@@ -240,6 +240,25 @@ def batch_workload(num: int = 256, seed: int = 4, *, n_range=(16, 40), depth_ran
     return out
 
 
+def serving_workload(num: int, seed: int = 5, *, n_range=(20, 64), depth_range=(8, 32),
+                     eps_range=(0.005, 0.05), logk_range=(14, 22)) -> List[Tuple[Circuit, dict]]:
+    """Requests of a serving run: uneven peaked circuits (random-pair
+    construction), each cut by top-K or, with probability 1/2, by p = 0.99
+    capped at K (p-mass alone can grow without bound)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(num):
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        d = int(rng.integers(depth_range[0], depth_range[1] + 1))
+        eps = float(rng.uniform(eps_range[0], eps_range[1]))
+        logk = int(rng.integers(logk_range[0], logk_range[1] + 1))
+        pmass = bool(rng.integers(0, 2))
+        cseed = int(rng.integers(0, 2**31 - 1))
+        c = peaked_circuit(n, d, eps, cseed, pairs="random", u3_layers=False, name=f"req{i}_n{n}_d{d}")
+        out.append((c, dict(K=1 << logk, p=0.99 if pmass else 0.0, precision="c64")))
+    return out
+
+
 def gate_arrays(gates: Sequence[Gate]):
     """Flatten a gate list into (m, qubits, U interleaved re/im float64) triples."""
     out = []

@@ -17,45 +17,16 @@
 #include <thread>
 #include <vector>
 
-#include "sts.h"
-#include "kernels.h"
+#include "runner.h"
 
 namespace {
+
+using namespace sts_runner;
 
 struct BatchJob {
     int idx;
     double work;
 };
-
-bool circuit_valid(const sts_circuit &c)
-{
-    if (c.n_qubits < 1 || c.n_qubits > 64) return false;
-    if (c.n_gates && (!c.gate_m || !c.gate_qubits || !c.gate_U || !c.truncate_after)) return false;
-    for (u64 i = 0; i < c.n_gates; ++i)
-        if (c.gate_m[i] < 1 || c.gate_m[i] > STS_MAXM) return false;
-    return true;
-}
-
-// terms a circuit's context must hold: K for truncated steps, and room for an
-// untruncated gate's 2^m x K candidates
-u64 circuit_cap(const sts_circuit &c)
-{
-    const u64 full = c.n_qubits >= 40 ? (1ull << 40) : (1ull << c.n_qubits);
-    u64 k = c.max_terms ? std::min<u64>(c.max_terms, full) : full;
-    int m_free = 0;
-    for (u64 i = 0; i < c.n_gates; ++i)
-        if (!c.truncate_after[i]) m_free = std::max(m_free, c.gate_m[i]);
-    u64 cap = k << m_free;
-    cap = std::min<u64>(std::max<u64>(cap, 1024), 1ull << 36);
-    return cap;
-}
-
-double circuit_work(const sts_circuit &c)
-{
-    const double full = c.n_qubits >= 40 ? 1e12 : (double)(1ull << c.n_qubits);
-    const double k = c.max_terms ? std::min((double)c.max_terms, full) : full;
-    return (double)c.n_gates * k;
-}
 
 struct Graphs {
     std::vector<hipGraph_t> g;
@@ -86,12 +57,8 @@ void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, voi
         const bool capturable = graph_steps > 0 && c.max_terms > 0 && m <= 3 && c.truncate_after[i] &&
                                 prev_truncated;
         if (!capturable) {
-            st = sts_apply_gate(ctx, m, c.gate_qubits + qo, c.gate_U + uo);
-            if (st == STS_OK && c.truncate_after[i]) st = sts_truncate(ctx);
             prev_truncated = c.truncate_after[i] != 0;
-            qo += (u64)m;
-            uo += 2ull << (2 * m);
-            ++i;
+            st = run_gates(ctx, c, i + 1, &i, &qo, &uo);
             continue;
         }
         // a chunk of consecutive truncated gates of up to 3 qubits: no call in
@@ -126,14 +93,12 @@ void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, voi
         if (e != hipSuccess) st = STS_E_HIP;
         prev_truncated = true;
     }
-    if (st == STS_OK) st = sts_peak(ctx, &r->peak_key, &r->peak_prob); // synchronises
-    if (st == STS_OK) st = sts_num_terms(ctx, &r->n_terms);
-    if (st == STS_OK) st = sts_counters(ctx, &r->gate_steps, &r->term_updates, nullptr);
-    if (st == STS_OK) st = sts_stats(ctx, nullptr, nullptr, &r->log10_cum_kept, nullptr);
+    if (st == STS_OK) st = finish(ctx, r);
     if (ctx) sts_free(ctx); // waits for the stream
     graphs.clear();
     r->status = st;
     r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    r->latency_seconds = r->seconds;
 }
 
 } // namespace

@@ -93,3 +93,15 @@ def test_batch_rejects_bad_config_without_running(lib):
         m[0] = bad
         assert lib.sts_batch_run(1, circ, ctypes.byref(_lib.BatchConfig(_lib.STS_C64, 2, 0)), res) == _lib.STS_E_ARG
     assert lib.sts_batch_run(0, None, ctypes.byref(_lib.BatchConfig(_lib.STS_C64, 2, 0)), None) == _lib.STS_OK
+
+
+def test_server_rejects_bad_config_without_running(lib):
+    import ctypes
+
+    from paper_2607_07816_amd import _lib
+    h = ctypes.c_void_p(0)
+    for cfg in (_lib.ServerConfig(_lib.STS_C64, 0, 1, 1, 0), _lib.ServerConfig(_lib.STS_C64, 1, 0, 1, 0),
+                _lib.ServerConfig(_lib.STS_C64, 1, 1, 0, 0), _lib.ServerConfig(9, 1, 1, 1, 0),
+                _lib.ServerConfig(_lib.STS_C64, 65, 1, 1, 0)):
+        assert lib.sts_server_create(ctypes.byref(h), ctypes.byref(cfg)) == _lib.STS_E_ARG and not h.value
+    lib.sts_server_destroy(None)  # NULL is a no-op
