@@ -408,41 +408,42 @@ constexpr int TT_NB = 128;
 
 template <typename AT> struct TileSmem {
     u64 key[TT_LD];
-    AT amp[TT_LD];
     u32 bkt[TT_LD];
 };
 
-// stage global terms [lo, hi) into LDS: every load of the thread is issued
-// before any of them is used, so the tile costs one memory latency, not nine
+// stage the keys of global terms [lo, hi) and their hash buckets into LDS:
+// every load of the thread is issued before any of them is used, so the tile
+// costs one memory latency. Amplitudes stay in global memory: a thread reads
+// its own term's (coalesced), and a group leader its members' (neighbours,
+// already in cache), which keeps the tile small and the occupancy high.
 template <typename AT, int M>
 __device__ __forceinline__ void stage_tile(TileSmem<AT> &s, const GateArg &g, const u64 *__restrict__ keys,
                                            const AT *__restrict__ amps, u64 lo, u64 hi)
 {
+    (void)amps;
     constexpr int PER = (TT_LD + STS_WG - 1) / STS_WG;
     const int sh = 64 - g.hb;
+    const int cnt = (int)(hi - lo);
     u64 kk[PER];
-    AT aa[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const u64 i = lo + (u64)r * STS_WG + threadIdx.x;
-        if (i < hi) {
-            kk[r] = keys[i];
-            aa[r] = amps[i];
-        }
+        const int li = r * STS_WG + (int)threadIdx.x;
+        if (li < cnt) kk[r] = keys[lo + li];
     }
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-        const u64 i = lo + (u64)r * STS_WG + threadIdx.x;
-        if (i < hi) {
-            const int li = r * STS_WG + (int)threadIdx.x;
+        const int li = r * STS_WG + (int)threadIdx.x;
+        if (li < cnt) {
             s.key[li] = kk[r];
-            s.amp[li] = aa[r];
             if (M > 0) s.bkt[li] = (u32)(sts_mix64(kk[r] & g.notmask) >> sh);
         }
     }
 }
 
-// the group led by term e (global index), from the staged tile [lo, hi)
+// the group led by term e (global index), from the staged tile [lo, hi).
+// Both scans walk LDS with 32-bit local indices; a run that reaches the edge
+// of the staged range (rare: the halo is 64 terms) continues in global memory
+// after the LDS loop.
 template <typename AT, int M>
 __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg &g, const u64 *__restrict__ keys,
                                            const AT *__restrict__ amps, u64 lo, u64 hi, u64 n, u64 e,
@@ -453,46 +454,47 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     if (e >= n) return;
     const int li = (int)(e - lo);
     const u64 key = s.key[li];
-    const AT amp = s.amp[li];
+    const AT amp = amps[e];
     if (M == 0) {
         G.rest = key;
         G.v[0] = amp;
         G.present = 1;
         return;
     }
-    const u64 rest = key & g.notmask;
+    const u64 nm = g.notmask;
+    const u64 rest = key & nm;
     const u32 b = s.bkt[li];
     const int sh = 64 - g.hb;
-    for (u64 p = e; p > 0; --p) {
-        const u64 q = p - 1;
-        u64 kq;
-        u32 bq;
-        if (q >= lo) {
-            kq = s.key[q - lo];
-            bq = s.bkt[q - lo];
-        } else {
-            kq = keys[q];
-            bq = (u32)(sts_mix64(kq & g.notmask) >> sh);
+    // backward: does an earlier member of this group lead it?
+    int p = li - 1;
+    for (; p >= 0; --p) {
+        if (s.bkt[p] != b) break;
+        if ((s.key[p] & nm) == rest) return;
+    }
+    if (p < 0 && lo > 0) { // the run goes on below the staged range
+        for (u64 q = lo; q > 0; --q) {
+            const u64 kq = keys[q - 1];
+            if ((u32)(sts_mix64(kq & nm) >> sh) != b) break;
+            if ((kq & nm) == rest) return;
         }
-        if (bq != b) break;
-        if ((kq & g.notmask) == rest) return; // an earlier member leads
     }
     G.rest = rest;
     group_clear<AT, M>(G);
     group_set<AT, M>(G, extract_bits<M>(key, g), amp);
-    for (u64 q = e + 1; q < n; ++q) {
-        const bool in = q < hi;
-        u64 kq;
-        u32 bq;
-        if (in) {
-            kq = s.key[q - lo];
-            bq = s.bkt[q - lo];
-        } else {
-            kq = keys[q];
-            bq = (u32)(sts_mix64(kq & g.notmask) >> sh);
+    // forward: collect the other members
+    const int last = (int)(hi - lo);
+    int f = li + 1;
+    for (; f < last; ++f) {
+        if (s.bkt[f] != b) break;
+        const u64 kf = s.key[f];
+        if ((kf & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kf, g), amps[lo + f]);
+    }
+    if (f == last) { // the run goes on above the staged range
+        for (u64 q = hi; q < n; ++q) {
+            const u64 kq = keys[q];
+            if ((u32)(sts_mix64(kq & nm) >> sh) != b) break;
+            if ((kq & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kq, g), amps[q]);
         }
-        if (bq != b) break;
-        if ((kq & g.notmask) == rest) group_set<AT, M>(G, extract_bits<M>(kq, g), in ? s.amp[q - lo] : amps[q]);
     }
 }
 
