@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=48, help="requests of the c5 workload")
     ap.add_argument("--load", type=float, default=0.7, help="c5 offered load, as a fraction of served capacity")
     ap.add_argument("--batch", type=int, default=256, help="circuits of the c4 workload")
+    ap.add_argument("--fuse", type=int, default=0, metavar="M",
+                    help="reorder and fuse the circuit into blocks of up to M qubits first (Sec. VI.A); 0 = off")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="terms in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -103,6 +105,11 @@ def main():
         circuit, cfg = C.workload_24q()
         prec = "c64"
     K, p = cfg["K"], cfg["p"]
+    if args.fuse:
+        from paper_2607_07816_amd import compile as CC
+        ng = len(circuit.gates)
+        circuit = CC.compile_circuit(circuit, args.fuse)
+        log(f"fused {ng} gates into {len(circuit.gates)} blocks of <= {args.fuse} qubits")
     amp_bytes = 8 if prec == "c64" else 16
     steps_avail = [i for i, t in enumerate(circuit.truncate_after) if t]
     need = args.warmup + args.steps + args.profile_steps + 1
@@ -120,7 +127,9 @@ def main():
         log(f"calibration copy of {args.copy_calibration} bytes done")
         del src, dst
     log(f"device {torch.cuda.get_device_name(dev)}; workload {circuit.name} n={circuit.n} K={K} p={p} {prec}")
-    st = State(circuit.n, K=K, p=p, precision=prec, capacity=K)
+    # 4-qubit blocks take the tiled passes when the state holds at most half
+    # of the capacity
+    st = State(circuit.n, K=K, p=p, precision=prec, capacity=2 * K if args.fuse >= 4 else K)
     gi = 0
 
     def run(nsteps):
@@ -202,6 +211,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": circuit.name + f"_K2^{K.bit_length() - 1}_p{p}_{prec}",
+            "fused_max_m": args.fuse,
             "n_qubits": circuit.n,
             "K": K,
             "p": p,

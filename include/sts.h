@@ -101,7 +101,10 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
 
 /*
  * Apply the gate U (host array, 2*4^m doubles, layout above) on the m
- * distinct qubits qubits[0..m-1] (each < n), 1 <= m <= 5. The result is
+ * distinct qubits qubits[0..m-1] (each < n), 1 <= m <= 5. Gates of up to 3
+ * qubits, and 4-qubit gates on a state holding at most about half of
+ * cap_terms, run on the LDS-tiled kernels; other 4- and 5-qubit gates run on
+ * slower untiled ones (same results). The result is
  * formed lazily: the grouping work runs now, and the new amplitudes are
  * produced by the following sts_truncate (so candidates are never stored),
  * or by the next call that needs them. Returns STS_E_ARG for bad arguments

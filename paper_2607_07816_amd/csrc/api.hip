@@ -231,12 +231,22 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     return b;
 }
 
-// workgroups of the histogram pass (persistent; m <= 3 walks 2048-term tiles),
-// at most as many as are resident at once
-int hist_groups(int prec, u64 n_bound, int m)
+// whether a gate of m qubits takes the LDS-tiled passes: always for m <= 3;
+// for m = 4 when every tile's side slab (2048 << 4 entries) fits the side
+// buffer, i.e. when the state holds at most about half the capacity
+bool use_tiles(const sts_ctx *c, int m)
 {
-    const u64 g = ceil_div(n_bound ? n_bound : 1, m <= 3 ? 2048 : STS_WG);
-    const u64 cap = (u64)std::min(group_hist_capacity(prec, m), STS_MAX_GROUPS);
+    if (m <= 3) return true;
+    if (m > 4) return false;
+    return ceil_div(std::max<u64>(c->n_bound, 1), 2048) * (2048ull << 4) <= c->scap;
+}
+
+// workgroups of the histogram pass (persistent; the tiled pass walks
+// 2048-term tiles), at most as many as are resident at once
+int hist_groups(int prec, u64 n_bound, int m, bool tiled)
+{
+    const u64 g = ceil_div(n_bound ? n_bound : 1, tiled ? 2048 : STS_WG);
+    const u64 cap = (u64)std::min(group_hist_capacity(prec, m, tiled), STS_MAX_GROUPS);
     return (int)std::min<u64>(std::max<u64>(g, 1), cap);
 }
 
@@ -294,8 +304,9 @@ sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
 sts_status count_candidates(sts_ctx *c, u64 *count)
 {
     PassBufs b = pass_bufs(c, c->cur, -1);
-    const int G = hist_groups(c->prec, c->n_bound, c->gate.m);
-    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, c->stream));
+    const bool tiled = use_tiles(c, c->gate.m);
+    const int G = hist_groups(c->prec, c->n_bound, c->gate.m, tiled);
+    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, tiled, c->stream));
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, 0, c->stream));
     const sts_status st = sync_ctl(c);
     if (st != STS_OK) return st;
@@ -322,7 +333,7 @@ sts_status materialise(sts_ctx *c)
     const int dst = (c->cur + 1) % 3;
     PassBufs b = pass_bufs(c, c->cur, dst);
     b.materialise = 1;
-    if (c->gate.m <= 3) {
+    if (use_tiles(c, c->gate.m)) {
         const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
         STS_LAUNCH(c, STS_K_TILE_KEPT, launch_tile_kept(b, tt, c->stream));
@@ -538,14 +549,14 @@ sts_status sts_truncate(sts_ctx *c)
     const u64 cb = sat_shl(c->n_bound, c->gate.m);
     const int out = (c->cur + 1) % 3;
     PassBufs b = pass_bufs(c, c->cur, out);
-    const int G = hist_groups(c->prec, c->n_bound, c->gate.m);
+    const bool tiled = use_tiles(c, c->gate.m);
+    const int G = hist_groups(c->prec, c->n_bound, c->gate.m, tiled);
     const int tiles = compact_tiles(c->n_bound, c->gate.m);
-    const bool tiled = c->gate.m <= 3;
+    const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
     b.predict = tiled ? 1 : 0; // the histogram pass also extracts the previous cut exponent
-    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, c->stream));
+    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, tiled, c->stream));
     b.predict = 0;
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, tiled ? 1 : 0, c->stream));
-    const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
     if (tiled) {
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
     } else {
@@ -555,7 +566,9 @@ sts_status sts_truncate(sts_ctx *c)
     }
     const int sg = (int)std::min<u64>(std::max<u64>(ceil_div(std::min(cb, c->scap), 256), 1), STS_SIDE_GROUPS);
     STS_LAUNCH(c, STS_K_SIDE_HIST, launch_side_hist(b, c->h2, sg, c->stream));
-    STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, sg, c->stream));
+    // the extraction has no per-workgroup state: one workgroup per tile slab
+    // keeps every slab's loads in flight at once
+    STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, tiled ? std::max(sg, tt) : sg, c->stream));
     STS_LAUNCH(c, STS_K_FINAL, launch_final(b, c->stream));
     u64 nb = c->K ? std::min<u64>(c->K, cb) : cb;
     if (nb > c->cap) {
@@ -592,8 +605,8 @@ sts_status sts_peak(sts_ctx *c, uint64_t *key, double *prob)
     if (st != STS_OK) return st;
     const GateArg g = identity_gate();
     PassBufs b = pass_bufs(c, c->cur, -1);
-    const int G = hist_groups(c->prec, c->n_bound, 0);
-    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, g, b, G, c->stream));
+    const int G = hist_groups(c->prec, c->n_bound, 0, true);
+    STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, g, b, G, true, c->stream));
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, 0, c->stream));
     st = sync_ctl(c);
     if (st != STS_OK) return st;

@@ -401,6 +401,7 @@ __device__ __forceinline__ u64 lb_pack(u32 epoch, u32 status, u64 val)
 // so every predecessor is resident or finished and the wait ends.
 __device__ inline u64 lb_exclusive(u64 *look, u64 stride, u64 tile, u64 local, u32 epoch)
 {
+    constexpr int B = 8; // predecessors read per round trip
     const u32 ep = epoch & 0xffffffu;
     if (tile == 0) {
         st_agent(&look[0], lb_pack(epoch, 2, local));
@@ -408,16 +409,27 @@ __device__ inline u64 lb_exclusive(u64 *look, u64 stride, u64 tile, u64 local, u
     }
     st_agent(&look[tile * stride], lb_pack(epoch, 1, local));
     u64 excl = 0;
-    u64 j = tile - 1;
-    while (true) {
-        const u64 v = ld_agent(&look[j * stride]);
-        if ((u32)(v >> 40) != ep) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
+    u64 j = tile - 1; // next predecessor to account for
+    for (;;) {
+        // tile 0 always publishes an inclusive value, so the walk ends at or
+        // before it; reads below tile 0 are never issued
+        u64 v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) v[b] = (u64)b <= j ? ld_agent(&look[(j - b) * stride]) : 0ull;
+        int used = 0;
+        bool done = false;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (done || used < b) continue;           // stopped earlier in this batch
+            if ((u64)b > j) continue;
+            if ((u32)(v[b] >> 40) != ep) continue;  // not published yet: re-read from here
+            excl += v[b] & STS_LB_VMASK;
+            used = b + 1;
+            if (((v[b] >> STS_LB_VBITS) & 3u) == 2u) done = true;
         }
-        excl += v & STS_LB_VMASK;
-        if (((v >> STS_LB_VBITS) & 3u) == 2u) break;
-        --j;
+        if (done) break;
+        if (used == 0) __builtin_amdgcn_s_sleep(1);
+        j -= (u64)used;
     }
     st_agent(&look[tile * stride], lb_pack(epoch, 2, excl + local));
     return excl;

@@ -1,17 +1,28 @@
-// group_c128_large.hip - instantiations of the gate-step kernels (group_impl.h) for
-// double2 amplitudes and gates of 4..5 qubits; compiled as a unit of
-// its own so the library builds in parallel.
+// group_c128_large.hip - instantiations of the gate-step kernels (group_impl.h)
+// for double2 amplitudes and gates of 4..5 qubits; compiled as a unit of its
+// own so the library builds in parallel.
 #include "group_impl.h"
 
 using namespace sts_group;
 
-hipError_t group_c128_large_hist(const GateArg &g, const PassBufs &b, int grid, hipStream_t s)
+hipError_t group_c128_large_hist(const GateArg &g, const PassBufs &b, int grid, bool tiled, hipStream_t s)
 {
+    if (g.m == 4 && tiled) return hist_m<double2, 4, true>(g, b, grid, s);
     switch (g.m) {
-    case 4: return hist_m<double2, 4>(g, b, grid, s);
-    case 5: return hist_m<double2, 5>(g, b, grid, s);
+    case 4: return hist_m<double2, 4, false>(g, b, grid, s);
+    case 5: return hist_m<double2, 5, false>(g, b, grid, s);
     }
     return hipErrorInvalidValue;
+}
+
+int group_c128_large_hist_capacity(int m, bool tiled)
+{
+    if (m == 4 && tiled) return hist_capacity<double2, 4, true>();
+    switch (m) {
+    case 4: return hist_capacity<double2, 4, false>();
+    case 5: return hist_capacity<double2, 5, false>();
+    }
+    return 1;
 }
 
 hipError_t group_c128_large_compact(int kind, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
@@ -23,11 +34,18 @@ hipError_t group_c128_large_compact(int kind, const GateArg &g, const PassBufs &
     return hipErrorInvalidValue;
 }
 
-int group_c128_large_hist_capacity(int m)
+hipError_t group_c128_large_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
-    switch (m) {
-    case 4: return hist_capacity<double2, 4>();
-    case 5: return hist_capacity<double2, 5>();
+    switch (g.m) {
+    case 4: return extract_tiles_m<double2, 4>(g, b, tiles, s);
     }
-    return 1;
+    return hipErrorInvalidValue;
+}
+
+hipError_t group_c128_large_emit_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
+{
+    switch (g.m) {
+    case 4: return emit_tiles_m<double2, 4>(g, b, tiles, s);
+    }
+    return hipErrorInvalidValue;
 }

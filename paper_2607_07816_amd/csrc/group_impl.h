@@ -23,10 +23,11 @@ template <typename AT> struct Scalar;
 template <> struct Scalar<double2> { typedef double T; };
 template <> struct Scalar<float2> { typedef float T; };
 
-// full unrolling only for gates of up to 3 qubits (the 32x32 case would
-// otherwise multiply the code size, for no gain off the hot path)
+// the loops over a group's outputs are unrolled for gates of up to 4
+// qubits, so per-output arrays stay in registers (the 32-output case would
+// multiply the code size; 5-qubit gates take the untiled passes)
 template <int M> struct Unroll {
-    static constexpr int value = M <= 3 ? (1 << M) : 1;
+    static constexpr int value = M <= 4 ? (1 << M) : 1;
 };
 
 template <typename AT, int M> struct Group {
@@ -139,8 +140,9 @@ __device__ __forceinline__ AT group_out(const GateArg &g, const Group<AT, M> &G,
     if (sizeof(R) == 4) {
         // complex64: fused multiply-adds (the FP32 path is held to a
         // tolerance, not to the FP64 operation order); absent members are
-        // zero and add nothing
-#pragma unroll Unroll<M>::value
+        // zero and add nothing. The member loop is always unrolled, so the
+        // group's registers are only indexed by constants.
+#pragma unroll
         for (int j = 0; j < (1 << M); ++j) {
             const R ur = UEntry<R, M>::re(g, i, j);
             const R ui = UEntry<R, M>::im(g, i, j);
@@ -154,7 +156,7 @@ __device__ __forceinline__ AT group_out(const GateArg &g, const Group<AT, M> &G,
         // complex128: the oracle's order - each product and sum rounded once,
         // members summed in ascending j; an absent member leaves the sum
         // untouched (selected away, not added as zero, so signed zeros match)
-#pragma unroll Unroll<M>::value
+#pragma unroll
         for (int j = 0; j < (1 << M); ++j) {
             const R ur = UEntry<R, M>::re(g, i, j);
             const R ui = UEntry<R, M>::im(g, i, j);
@@ -391,18 +393,17 @@ __global__ void __launch_bounds__(STS_WG) k_group_compact(GateArg g, PassBufs b)
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled passes (gates of up to 3 qubits). A workgroup stages a tile of
-// TT_TG sorted terms plus a halo of TT_H on each side (keys, amplitudes and
-// hash buckets) in LDS, so the partner search reads LDS; a run that crosses
-// the halo continues in global memory. Compaction passes claim TT_BATCH
-// consecutive tiles per atomic; a batch of more than one tile serialises the
-// look-back (a batch's first tile waits for the previous batch's last).
+// LDS-tiled passes (gates of up to 4 qubits). A workgroup stages a tile of
+// TT_TG sorted terms plus a halo of TT_H on each side (keys and hash
+// buckets) in LDS, so the partner search reads LDS; a run that crosses the
+// halo continues in global memory. Tile t owns slab t of the side buffer
+// (2048 << m entries) and writes its survivors at an offset from a scan of
+// per-tile counts, so no pass needs atomics across workgroups.
 // ---------------------------------------------------------------------------
 constexpr int TT_IT = 8;
 constexpr int TT_TG = STS_WG * TT_IT;   // 2048 terms per tile
 constexpr int TT_H = 64;
 constexpr int TT_LD = TT_TG + 2 * TT_H;
-constexpr int TT_BATCH = 1;
 constexpr int TT_EBASE = 1023 - 127 + 8; // exponent fields [904, 1032) live in LDS bins
 constexpr int TT_NB = 128;
 
@@ -699,119 +700,8 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
     }
 }
 
-// compaction passes over tiles: EXTRACT (side buffer) or EMIT (new state)
-template <typename AT, int M, int KIND>
-__global__ void __launch_bounds__(STS_WG) k_tile_compact(GateArg g, PassBufs b)
-{
-    typedef typename Scalar<AT>::T R;
-    __shared__ TileSmem<AT> s;
-    __shared__ u32 s_tile;
-    __shared__ u32 s_scratch[STS_WG / 64];
-    __shared__ u64 s_base;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        const u32 t = atomicAdd(b.tile_ctr, (u32)TT_BATCH);
-        if (t == (gridDim.x - 1) * TT_BATCH) st_agent(b.tile_ctr, 0u); // last claim: reset
-        s_tile = t;
-    }
-    __syncthreads();
-    const u64 first_tile = s_tile;
-    DevCtl *ctl = b.ctl;
-    const int materialise = b.materialise;
-    if (KIND == STS_KIND_EXTRACT && ctl->keep_all) return;
-    const u64 n = *b.n_in;
-    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
-    if (first_tile >= ntiles) {
-        if (first_tile == 0 && tid == 0) { // empty input: publish the empty result
-            if (KIND == STS_KIND_EXTRACT) ctl->side_n = 0;
-            else *b.n_out = 0;
-        }
-        return;
-    }
-    const bool keep_everything = KIND == STS_KIND_EMIT && (materialise || ctl->keep_all);
-    const int e_star = ctl->e_star;
-    const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
-    const bool rescale = KIND == STS_KIND_EMIT && !materialise && !ctl->keep_all && ctl->dropped;
-    const double scale = ctl->scale;
-    const u64 *keys = b.keys;
-    const AT *amps = (const AT *)b.amps;
-    const u64 cap = KIND == STS_KIND_EXTRACT ? b.side_cap : b.out_cap;
-
-    for (u64 tile = first_tile; tile < first_tile + TT_BATCH && tile < ntiles; ++tile) {
-        const u64 base = tile * TT_TG;
-        const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
-        const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
-        __syncthreads();
-        stage_tile<AT, M>(s, g, keys, amps, lo, hi);
-        __syncthreads();
-        // count
-        u32 mine = 0;
-#pragma unroll 1
-        for (int k = 0; k < TT_IT; ++k) {
-            const u64 e = base + (u64)k * STS_WG + tid;
-            Group<AT, M> G;
-            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
-            if (!G.present) continue;
-#pragma unroll Unroll<M>::value
-            for (int i = 0; i < (1 << M); ++i) {
-                const AT o = group_out<AT, M>(g, G, i);
-                const u64 key = G.rest | deposit_bits<M>((u32)i, g);
-                const bool keep = keep_everything ? (M == 0 || nonzero(o))
-                                                  : keep_out<AT, M, KIND>(ctl, materialise, o, key, e_star, thr_w,
-                                                                          thr_k);
-                mine += keep ? 1u : 0u;
-            }
-        }
-        u32 tile_total;
-        const u32 my_off = block_excl_scan<u32, STS_WG>(mine, s_scratch, &tile_total);
-        if (tid == 0) s_base = lb_exclusive(b.look, 1, tile, tile_total, b.epoch);
-        __syncthreads();
-        u64 pos = s_base + my_off;
-        if (tid == 0 && tile == ntiles - 1) {
-            const u64 total = s_base + tile_total;
-            if (KIND == STS_KIND_EXTRACT) ctl->side_n = total;
-            else *b.n_out = total;
-        }
-        if (mine == 0) continue;
-        // write
-#pragma unroll 1
-        for (int k = 0; k < TT_IT; ++k) {
-            const u64 e = base + (u64)k * STS_WG + tid;
-            Group<AT, M> G;
-            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
-            if (!G.present) continue;
-#pragma unroll Unroll<M>::value
-            for (int i = 0; i < (1 << M); ++i) {
-                AT o = group_out<AT, M>(g, G, i);
-                const u64 key = G.rest | deposit_bits<M>((u32)i, g);
-                const bool keep = keep_everything ? (M == 0 || nonzero(o))
-                                                  : keep_out<AT, M, KIND>(ctl, materialise, o, key, e_star, thr_w,
-                                                                          thr_k);
-                if (!keep) continue;
-                if (pos >= cap) {
-                    atomicOr(&ctl->flags, KIND == STS_KIND_EXTRACT ? STS_F_SIDE_OVERFLOW : STS_F_OUT_OVERFLOW);
-                    ++pos;
-                    continue;
-                }
-                if (KIND == STS_KIND_EXTRACT) {
-                    b.side_key[pos] = key;
-                    b.side_w[pos] = weight_bits(o);
-                } else {
-                    if (rescale) {
-                        o.x = (R)((double)o.x * scale);
-                        o.y = (R)((double)o.y * scale);
-                    }
-                    b.out_keys[pos] = key;
-                    ((AT *)b.out_amps)[pos] = o;
-                }
-                ++pos;
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// atomic-free compaction (gates of up to 3 qubits), one workgroup per tile:
+// atomic-free compaction (gates of up to 4 qubits), one workgroup per tile:
 //   k_tile_extract - counts the tile's candidates ranked certainly before the
 //                    cut (exponent field above e*, or all when nothing is
 //                    cut) and copies those of exponent e* into the tile's own
@@ -949,13 +839,15 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(GateArg g, PassBufs b)
 
 // workgroups of the histogram pass that fit on the device at once (the pass
 // is persistent: more would run as a second, mostly idle wave)
-template <typename AT, int M> int hist_capacity()
+template <typename AT, int M, bool TILED> int hist_capacity()
 {
     static int cap = 0;
     if (!cap) {
         int per_cu = 0, dev = 0, cus = 0;
-        if (M <= 3) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_hist<AT, M>, STS_WG, 0);
-        else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_group_hist<AT, M>, STS_WG, 0);
+        if constexpr (TILED)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_hist<AT, M>, STS_WG, 0);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_group_hist<AT, M>, STS_WG, 0);
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         cap = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
@@ -963,9 +855,10 @@ template <typename AT, int M> int hist_capacity()
     return cap;
 }
 
-template <typename AT, int M> hipError_t hist_m(const GateArg &g, const PassBufs &b, int grid, hipStream_t s)
+template <typename AT, int M, bool TILED>
+hipError_t hist_m(const GateArg &g, const PassBufs &b, int grid, hipStream_t s)
 {
-    if (M <= 3) hipLaunchKernelGGL((k_tile_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
+    if constexpr (TILED) hipLaunchKernelGGL((k_tile_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
     else hipLaunchKernelGGL((k_group_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
     return hipGetLastError();
 }
@@ -973,14 +866,6 @@ template <typename AT, int M> hipError_t hist_m(const GateArg &g, const PassBufs
 template <typename AT, int M>
 hipError_t compact_m(int kind, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
-    if (M <= 3) {
-        // tiles: launched workgroups, each claiming TT_BATCH tiles of TT_TG terms
-        if (kind == STS_KIND_EXTRACT)
-            hipLaunchKernelGGL((k_tile_compact<AT, M, STS_KIND_EXTRACT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
-        else
-            hipLaunchKernelGGL((k_tile_compact<AT, M, STS_KIND_EMIT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
-        return hipGetLastError();
-    }
     if (kind == STS_KIND_EXTRACT)
         hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EXTRACT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
     else

@@ -63,8 +63,8 @@ hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kou
                              u64 *look, u32 *tile_ctr, const u32 *epoch_base, int pass, int tiles,
                              hipStream_t s);
 
-hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, hipStream_t s);
-int group_hist_capacity(int prec, int m); // resident workgroups of the histogram pass
+hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, bool tiled, hipStream_t s);
+int group_hist_capacity(int prec, int m, bool tiled); // resident workgroups of the histogram pass
 hipError_t launch_group_compact(int prec, int kind, const GateArg &g, const PassBufs &b, int tiles,
                                 hipStream_t s);
 hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, int predicted, hipStream_t s);

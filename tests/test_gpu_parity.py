@@ -278,3 +278,24 @@ def test_argument_errors(S):
         # nothing changed
         assert st.num_terms() == 1
         assert st.peak() == (0, 1.0)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("cap_factor", [1, 4])
+def test_four_qubit_gate_tiled_and_untiled(S, prec, cap_factor):
+    # a state filling its capacity takes the untiled passes for a 4-qubit
+    # gate; one at a quarter of it takes the tiled passes (larger side slabs)
+    rng = np.random.default_rng(404)
+    n, N, K = 20, 5000, 2000
+    keys, amps = random_state(rng, n, N)
+    qs, U = C.haar_unitary(rng, 16), None
+    qubits = tuple(int(q) for q in rng.choice(n, size=4, replace=False))
+    U = C.haar_unitary(rng, 16)
+    say(f"[m4] {prec} N={N} cap={N * cap_factor} K={K} qubits={qubits}")
+    kg, ag, sg = gpu_step(S, keys, amps, n, qubits, U, K, 0.0, prec=prec, cap=N * cap_factor)
+    ko, ao, info = oracle_step(keys, amps, qubits, U, K, 0.0)
+    if prec == "c128":
+        assert_same_fp64(kg, ag, ko, ao)
+    else:
+        assert np.array_equal(kg, ko)
+        assert np.abs(ag - ao).max() <= 1e-5
