@@ -536,7 +536,7 @@ template <int BITS> __device__ __forceinline__ u32 wave_claim_n(u32 cnt, u32 *co
 // LDS bins of the histogram pass: TT_NB exponent fields from TT_EBASE, in
 // TT_COPIES copies (lane % TT_COPIES picks one) so that lanes hitting the same
 // hot exponent do not all serialise on one address
-constexpr int TT_COPIES = 4;
+constexpr int TT_COPIES = 2;
 
 // add the LDS bins to the global exponent histogram and clear them
 __device__ __forceinline__ void flush_bins(const PassBufs &b, u64 *s_hi, u64 *s_lo)

@@ -92,6 +92,6 @@ inline u64 sts_compact_groups(u64 n, int m)
 #define STS_KIND_EMIT 1
 #define STS_GROUP_ITEMS 4                       // elements per thread in a compaction tile
 #define STS_GTILE (STS_WG * STS_GROUP_ITEMS)     // elements per compaction tile
-#define STS_MAX_GROUPS 1024                      // persistent grid of the histogram pass
+#define STS_MAX_GROUPS 2048                      // workgroups of a histogram pass (best-term slots)
 #define STS_SIDE_GROUPS 512
 #define STS_SUB_CAP (1u << 16)                   // level-2 subset buffer (terms)
