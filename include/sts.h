@@ -147,8 +147,8 @@ sts_status sts_counters(sts_ctx *ctx, uint64_t *gate_steps, uint64_t *term_updat
 
 /* Kernel kinds timed by sts_profile (the kernels of a gate step). */
 typedef enum {
-    STS_K_RADIX_HIST = 0,   /* digit histogram of the grouping sort          */
-    STS_K_RADIX_SCAN = 1,   /* digit offsets                                 */
+    STS_K_RADIX_HIST = 0,   /* per-tile digit counts of a grouping-sort pass */
+    STS_K_RADIX_SCAN = 1,   /* their scan into per-tile digit offsets        */
     STS_K_RADIX_PASS = 2,   /* one scatter pass of the grouping sort         */
     STS_K_GROUP_HIST = 3,   /* gate + weight histogram pass                  */
     STS_K_PICK1 = 4,        /* exponent-level cut                            */

@@ -3,8 +3,9 @@
 //
 // A gate step (sts_apply_gate then sts_truncate) runs, on the context's
 // stream and without host synchronisation:
-//   1. radix histogram + scan + 1..4 scatter passes: group the state by the
-//      hash bucket of the bits outside the gate (radix.hip);
+//   1. 1..4 radix digit passes (per-tile counts, per-digit scan, scatter):
+//      group the state by the hash bucket of the bits outside the gate
+//      (radix.hip);
 //   2. histogram pass: recompute every new amplitude, histogram its weight by
 //      exponent field with exact mantissa sums (group.hip);
 //   3. level-1 pick: exact prefix over exponent bins (select.hip);
@@ -36,7 +37,7 @@ u64 align_up(u64 x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
-    u64 ctl, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rhist, roffs, look_radix, look_comp,
+    u64 ctl, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
         t_above, t_side, t_off, tctr, dU, total;
 };
 
@@ -69,9 +70,9 @@ Layout make_layout(u64 cap, int prec)
     L.h1 = take(3 * STS_NBIN * 8);
     L.h2 = take(3 * STS_NBIN * 8);
     L.best = take(2 * STS_MAX_GROUPS * 8);
-    L.rhist = take(STS_MAX_PASSES * 256 * 8);
-    L.roffs = take(STS_MAX_PASSES * 256 * 8);
-    L.look_radix = take(STS_MAX_PASSES * tiles * 256 * 8);
+    L.rcount = take(256 * tiles * 4);
+    L.rprefix = take(256 * tiles * 8);
+    L.rtotal = take(256 * 8);
     L.look_comp = take(gtiles * 8);
     L.t_above = take(ttiles * 4);
     L.t_side = take(ttiles * 4);
@@ -102,7 +103,8 @@ struct sts_ctx {
     DevCtl *ctl = nullptr;
     u64 *h1 = nullptr, *h2 = nullptr, *best = nullptr;
     u64 *side_key = nullptr, *side_w = nullptr, *sub_key = nullptr, *sub_w = nullptr;
-    u64 *rhist = nullptr, *roffs = nullptr, *look_radix = nullptr, *look_comp = nullptr;
+    u32 *rcount = nullptr;                          // per-tile digit counts of a scatter pass
+    u64 *rprefix = nullptr, *rtotal = nullptr, *look_comp = nullptr;
     u32 *t_above = nullptr, *t_side = nullptr;
     u64 *t_off = nullptr;
     u32 *tctr = nullptr;
@@ -187,7 +189,6 @@ u32 next_epoch(sts_ctx *c)
 {
     if (++c->epoch >= (1u << 24)) {
         // tags wrap: clear every look-back word once
-        (void)hipMemsetAsync(c->look_radix, 0, STS_MAX_PASSES * c->tiles_cap * 256 * 8, c->stream);
         (void)hipMemsetAsync(c->look_comp, 0, c->gtiles_cap * 8, c->stream);
         c->epoch = 1;
     }
@@ -279,19 +280,18 @@ sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
     int npass = (lg + 7) / 8;
     npass = std::min(std::max(npass, 1), STS_MAX_PASSES);
     const int hb = 8 * npass;
-    const int grid = (int)std::min<u64>(std::max<u64>(ceil_div(nb, STS_WG * 8), 1), 1024);
-    STS_LAUNCH(c, STS_K_RADIX_HIST, launch_radix_hist(c->keys[c->cur], &c->ctl->cnt[c->cur], notmask, hb, npass, c->rhist, grid,
-                                 c->stream));
-    STS_LAUNCH(c, STS_K_RADIX_SCAN, launch_radix_scan(c->rhist, c->roffs, npass, &c->ctl->radix_epoch, c->stream));
     const int tiles = (int)std::max<u64>(ceil_div(nb, STS_TILE), 1);
     const int a = (c->cur + 1) % 3, b = (c->cur + 2) % 3;
     int src = c->cur, dst = a;
     for (int p = 0; p < npass; ++p) {
         const int shift = 64 - hb + 8 * p;
+        STS_LAUNCH(c, STS_K_RADIX_HIST, launch_radix_count(c->keys[src], &c->ctl->cnt[src], notmask, shift, c->rcount,
+                                                            c->tiles_cap, tiles, c->stream));
+        STS_LAUNCH(c, STS_K_RADIX_SCAN, launch_radix_scan(c->rcount, c->rprefix, c->rtotal, &c->ctl->cnt[src],
+                                                           c->tiles_cap, c->stream));
         STS_LAUNCH(c, STS_K_RADIX_PASS, launch_radix_pass(c->prec, c->keys[src], c->amps[src], c->keys[dst], c->amps[dst],
-                                     &c->ctl->cnt[src], &c->ctl->cnt[dst], notmask, shift, c->roffs + 256 * p,
-                                     c->look_radix + (u64)p * c->tiles_cap * 256, c->tctr + p,
-                                     &c->ctl->radix_epoch, p, tiles, c->stream));
+                                     &c->ctl->cnt[src], &c->ctl->cnt[dst], notmask, shift, c->rprefix, c->rtotal,
+                                     c->tiles_cap, tiles, c->stream));
         src = dst;
         dst = dst == a ? b : a;
     }
@@ -445,9 +445,9 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     c->h1 = (u64 *)(c->mem + L.h1);
     c->h2 = (u64 *)(c->mem + L.h2);
     c->best = (u64 *)(c->mem + L.best);
-    c->rhist = (u64 *)(c->mem + L.rhist);
-    c->roffs = (u64 *)(c->mem + L.roffs);
-    c->look_radix = (u64 *)(c->mem + L.look_radix);
+    c->rcount = (u32 *)(c->mem + L.rcount);
+    c->rprefix = (u64 *)(c->mem + L.rprefix);
+    c->rtotal = (u64 *)(c->mem + L.rtotal);
     c->look_comp = (u64 *)(c->mem + L.look_comp);
     c->t_above = (u32 *)(c->mem + L.t_above);
     c->t_side = (u32 *)(c->mem + L.t_side);

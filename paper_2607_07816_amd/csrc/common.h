@@ -44,7 +44,6 @@ struct DevCtl {
     u64 sub_n;           // side-buffer terms copied to the level-2 subset buffer
     u32 done[4];         // last-workgroup counters, one per kernel kind
     u32 flags;           // STS_F_* below
-    u32 radix_epoch;     // look-back tag of the current sort's first pass (advanced on the device)
     // truncation rule
     u64 K;               // top-k (0 = off)
     double p;            // p-mass (off unless 0 < p < 1)

@@ -55,13 +55,13 @@ struct PassBufs {
 };
 
 // launch helpers (return hipError_t of the launch)
-hipError_t launch_radix_hist(const u64 *keys, const u64 *n_in, u64 notmask, int hb, int npass,
-                             u64 *hist, int grid, hipStream_t s);
-hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, u32 *epoch, hipStream_t s);
-hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout,
-                             const u64 *n_in, u64 *n_out, u64 notmask, int shift, const u64 *offs,
-                             u64 *look, u32 *tile_ctr, const u32 *epoch_base, int pass, int tiles,
+hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, u64 notmask, int shift, u32 *counts,
+                              u64 tiles_cap, int tiles, hipStream_t s);
+hipError_t launch_radix_scan(const u32 *counts, u64 *prefix, u64 *totals, const u64 *n_in, u64 tiles_cap,
                              hipStream_t s);
+hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout, const u64 *n_in,
+                             u64 *n_out, u64 notmask, int shift, const u64 *prefix, const u64 *totals,
+                             u64 tiles_cap, int tiles, hipStream_t s);
 
 hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, bool tiled, hipStream_t s);
 int group_hist_capacity(int prec, int m, bool tiled); // resident workgroups of the histogram pass

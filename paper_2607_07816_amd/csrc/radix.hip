@@ -8,11 +8,16 @@
 // bucket, so after the sort every group sits inside one short run of equal
 // buckets; the hash spreads buckets evenly whatever the key distribution.
 //
-// Kernels: one histogram pass over the keys for every digit, a 256-bin scan,
-// then one scatter pass per digit. Each scatter pass ranks a 4096-key tile in
-// registers and LDS (wave64 ballots find lanes with equal digits), gets the
-// tile's global offsets with decoupled look-back, stages the tile in LDS in
-// digit order and writes keys and amplitudes out in coalesced runs.
+// Each digit pass is reduce-then-scan, with no waiting between workgroups:
+//   k_radix_count - per 4096-key tile, the count of every digit
+//   k_radix_scan  - per digit (one workgroup each), the exclusive prefix of
+//                   its counts over the tiles, and its total
+//   k_radix_pass  - per tile: rank the keys in registers and LDS (wave64
+//                   ballots find lanes with equal digits), take the tile's
+//                   output offsets from the scan (digit base = exclusive scan
+//                   of the totals, done in the workgroup), stage the tile in
+//                   LDS in digit order and write keys and amplitudes out in
+//                   coalesced runs.
 #include "kernels.h"
 
 namespace {
@@ -22,91 +27,98 @@ __device__ __forceinline__ u32 bucket_digit(u64 key, u64 notmask, int shift)
     return (u32)((sts_mix64(key & notmask) >> shift) & 255u);
 }
 
-__global__ void __launch_bounds__(STS_WG) k_radix_hist(const u64 *__restrict__ keys, const u64 *n_in,
-                                                        u64 notmask, int hb, int npass,
-                                                        u64 *__restrict__ hist)
+// digit counts of one tile, written digit-major: counts[d * tiles_cap + tile]
+__global__ void __launch_bounds__(STS_WG) k_radix_count(const u64 *__restrict__ keys, const u64 *n_in, u64 notmask,
+                                                         int shift, u32 *__restrict__ counts, u64 tiles_cap)
 {
-    __shared__ u32 s_h[STS_MAX_PASSES * 256];
-    for (int i = threadIdx.x; i < STS_MAX_PASSES * 256; i += STS_WG) s_h[i] = 0;
+    __shared__ u32 s_h[256];
+    s_h[threadIdx.x] = 0;
     __syncthreads();
     const u64 n = *n_in;
-    const int base_shift = 64 - hb;
-    constexpr int IT = 8; // keys per thread per round, loaded before use
-    for (u64 r = (u64)blockIdx.x * STS_WG * IT; r < n; r += (u64)gridDim.x * STS_WG * IT) {
-        u64 kk[IT];
+    const u64 tile = blockIdx.x;
+    const u64 base = tile * STS_TILE;
+    u64 kk[STS_TILE_ITEMS];
 #pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            const u64 i = r + (u64)k * STS_WG + threadIdx.x;
-            kk[k] = i < n ? keys[i] : 0ull;
-        }
+    for (int k = 0; k < STS_TILE_ITEMS; ++k) {
+        const u64 i = base + (u64)k * STS_WG + threadIdx.x;
+        kk[k] = i < n ? keys[i] : 0ull;
+    }
 #pragma unroll
-        for (int k = 0; k < IT; ++k) {
-            const u64 i = r + (u64)k * STS_WG + threadIdx.x;
-            if (i >= n) continue;
-            const u64 h = sts_mix64(kk[k] & notmask);
-            for (int p = 0; p < npass; ++p) {
-                const u32 d = (u32)((h >> (base_shift + 8 * p)) & 255u);
-                atomicAdd(&s_h[p * 256 + d], 1u);
-            }
-        }
+    for (int k = 0; k < STS_TILE_ITEMS; ++k) {
+        const u64 i = base + (u64)k * STS_WG + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[bucket_digit(kk[k], notmask, shift)], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < npass * 256; i += STS_WG) {
-        const u32 c = s_h[i];
-        if (c) atomicAdd(&hist[i], (u64)c);
-    }
+    counts[(u64)threadIdx.x * tiles_cap + tile] = s_h[threadIdx.x];
 }
 
-// exclusive scan of each pass's 256 digit counts; clears the histogram and
-// advances the look-back tags (on the device, so a replayed graph of these
-// launches never meets tags of an earlier replay)
-__global__ void __launch_bounds__(256) k_radix_scan(u64 *__restrict__ hist, u64 *__restrict__ offs, int npass,
-                                                    u32 *epoch)
+// per digit (workgroup d): exclusive prefix of its tile counts, and its
+// total, both digit-major (coalesced; every load of a thread in flight at
+// once): prefix[d * tiles_cap + tile].
+__global__ void __launch_bounds__(STS_WG) k_radix_scan(const u32 *__restrict__ counts, u64 *__restrict__ prefix,
+                                                        u64 *__restrict__ totals, const u64 *n_in, u64 tiles_cap)
 {
-    __shared__ u64 scratch[4];
-    if (threadIdx.x == 0) {
-        u32 e = *epoch + STS_MAX_PASSES;
-        if (e >= (1u << 24) - STS_MAX_PASSES) e = 1;
-        *epoch = e;
+    constexpr int CH = 16;
+    __shared__ u64 scratch[STS_WG / 64];
+    __shared__ u64 s_carry;
+    const u64 n = *n_in;
+    const u64 ntiles = (n + STS_TILE - 1) / STS_TILE;
+    const u64 d = blockIdx.x;
+    const u32 *c = counts + d * tiles_cap;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    // chunks of STS_WG * CH tiles: thread t owns tiles [t*CH, t*CH+CH) of a chunk
+    for (u64 c0 = 0; c0 < ntiles; c0 += (u64)STS_WG * CH) {
+        const u64 lo = c0 + (u64)threadIdx.x * CH;
+        u32 v[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) v[k] = lo + k < ntiles ? c[lo + k] : 0u;
+        u64 sum = 0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) sum += v[k];
+        u64 total;
+        u64 run = block_excl_scan<u64, STS_WG>(sum, scratch, &total) + s_carry;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (lo + k < ntiles) prefix[d * tiles_cap + lo + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += total;
+        __syncthreads();
     }
-    for (int p = 0; p < npass; ++p) {
-        const u64 v = hist[p * 256 + threadIdx.x];
-        u64 tot;
-        const u64 ex = block_excl_scan<u64, 256>(v, scratch, &tot);
-        offs[p * 256 + threadIdx.x] = ex;
-        hist[p * 256 + threadIdx.x] = 0;
-    }
+    if (threadIdx.x == 0) totals[d] = s_carry;
 }
 
 template <typename AT>
 __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ kin, const AT *__restrict__ ain,
                                                         u64 *__restrict__ kout, AT *__restrict__ aout,
                                                         const u64 *n_in, u64 *n_out, u64 notmask, int shift,
-                                                        const u64 *__restrict__ offs, u64 *__restrict__ look,
-                                                        u32 *tile_ctr, const u32 *epoch_base, int pass)
+                                                        const u64 *__restrict__ prefix,
+                                                        const u64 *__restrict__ totals, u64 tiles_cap)
 {
     constexpr int NW = STS_WG / 64;
     constexpr int IT = STS_TILE_ITEMS;
     constexpr int ESZ = sizeof(AT) > sizeof(u64) ? sizeof(AT) : sizeof(u64);
-    __shared__ u32 s_tile;
     __shared__ u32 s_cnt[NW][256];
     __shared__ u32 s_dstart[256];
     __shared__ u64 s_base[256];
     __shared__ u32 s_scratch[NW];
+    __shared__ u64 s_scratch64[NW];
     __shared__ unsigned char s_dig[STS_TILE];
     __shared__ __attribute__((aligned(16))) unsigned char s_buf[STS_TILE * ESZ];
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
-    if (tid == 0) {
-        const u32 t = atomicAdd(tile_ctr, 1u);
-        if (t == gridDim.x - 1) st_agent(tile_ctr, 0u); // last id handed out: reset for the next launch
-        s_tile = t;
-    }
     for (int i = tid; i < NW * 256; i += STS_WG) (&s_cnt[0][0])[i] = 0;
+    // global offset of this tile's first key of digit tid: the digit's base
+    // (exclusive scan of the totals) plus the tiles before it; loaded now,
+    // used after the ranking
+    const u64 tile = blockIdx.x;
+    const u64 tot_d = totals[tid];
+    const u64 pre_d = prefix[(u64)tid * tiles_cap + tile];
     __syncthreads();
-    const u64 tile = s_tile;
     const u64 n = *n_in;
     if (tile == 0 && tid == 0) *n_out = n;
     const u64 base = tile * STS_TILE;
@@ -165,9 +177,9 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     u32 all;
     const u32 dstart = block_excl_scan<u32, STS_WG>(tot, s_scratch, &all);
     s_dstart[tid] = dstart;
-    // global position of this tile's first key with digit tid
-    const u64 excl = lb_exclusive(look + tid, 256, tile, tot, *epoch_base + (u32)pass);
-    s_base[tid] = offs[tid] + excl;
+    u64 n_all;
+    const u64 dbase = block_excl_scan<u64, STS_WG>(tot_d, s_scratch64, &n_all);
+    s_base[tid] = dbase + pre_d;
     __syncthreads();
 
     // stage keys in digit order, then write them out
@@ -204,28 +216,29 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
 
 } // namespace
 
-hipError_t launch_radix_hist(const u64 *keys, const u64 *n_in, u64 notmask, int hb, int npass, u64 *hist, int grid,
-                             hipStream_t s)
+hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, u64 notmask, int shift, u32 *counts,
+                              u64 tiles_cap, int tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(STS_WG), 0, s, keys, n_in, notmask, hb, npass, hist);
+    hipLaunchKernelGGL(k_radix_count, dim3(tiles), dim3(STS_WG), 0, s, keys, n_in, notmask, shift, counts, tiles_cap);
     return hipGetLastError();
 }
 
-hipError_t launch_radix_scan(u64 *hist, u64 *offs, int npass, u32 *epoch, hipStream_t s)
+hipError_t launch_radix_scan(const u32 *counts, u64 *prefix, u64 *totals, const u64 *n_in, u64 tiles_cap,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, hist, offs, npass, epoch);
+    hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(STS_WG), 0, s, counts, prefix, totals, n_in, tiles_cap);
     return hipGetLastError();
 }
 
 hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout, const u64 *n_in,
-                             u64 *n_out, u64 notmask, int shift, const u64 *offs, u64 *look, u32 *tile_ctr,
-                             const u32 *epoch_base, int pass, int tiles, hipStream_t s)
+                             u64 *n_out, u64 notmask, int shift, const u64 *prefix, const u64 *totals,
+                             u64 tiles_cap, int tiles, hipStream_t s)
 {
     if (prec == 0)
         hipLaunchKernelGGL(k_radix_pass<double2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const double2 *)ain,
-                           kout, (double2 *)aout, n_in, n_out, notmask, shift, offs, look, tile_ctr, epoch_base, pass);
+                           kout, (double2 *)aout, n_in, n_out, notmask, shift, prefix, totals, tiles_cap);
     else
         hipLaunchKernelGGL(k_radix_pass<float2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const float2 *)ain, kout,
-                           (float2 *)aout, n_in, n_out, notmask, shift, offs, look, tile_ctr, epoch_base, pass);
+                           (float2 *)aout, n_in, n_out, notmask, shift, prefix, totals, tiles_cap);
     return hipGetLastError();
 }
