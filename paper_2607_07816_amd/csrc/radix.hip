@@ -38,10 +38,15 @@ __global__ void __launch_bounds__(STS_WG) k_radix_count(const u64 *__restrict__ 
     const u64 tile = blockIdx.x;
     const u64 base = tile * STS_TILE;
     u64 kk[STS_TILE_ITEMS];
+    if (base + STS_TILE <= n) {
 #pragma unroll
-    for (int k = 0; k < STS_TILE_ITEMS; ++k) {
-        const u64 i = base + (u64)k * STS_WG + threadIdx.x;
-        kk[k] = i < n ? keys[i] : 0ull;
+        for (int k = 0; k < STS_TILE_ITEMS; ++k) kk[k] = keys[base + (u64)k * STS_WG + threadIdx.x];
+    } else {
+#pragma unroll
+        for (int k = 0; k < STS_TILE_ITEMS; ++k) {
+            const u64 i = base + (u64)k * STS_WG + threadIdx.x;
+            kk[k] = i < n ? keys[i] : 0ull;
+        }
     }
 #pragma unroll
     for (int k = 0; k < STS_TILE_ITEMS; ++k) {
@@ -129,14 +134,24 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     AT amp[IT];
     u32 dig[IT];
     u32 rank[IT];
+    if (base + STS_TILE <= n) {
+        // a full tile (uniform branch): every load issued back to back
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-        const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
-        if (e < n) {
+        for (int k = 0; k < IT; ++k) {
+            const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
             key[k] = kin[e];
             amp[k] = ain[e];
-        } else {
-            key[k] = 0ull;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
+            if (e < n) {
+                key[k] = kin[e];
+                amp[k] = ain[e];
+            } else {
+                key[k] = 0ull;
+            }
         }
     }
     // rank every key of the tile among equal digits, in index order
