@@ -41,11 +41,14 @@ struct DevCtl {
     u64 side_ntiles;     // tiled layout: tiles, each owning a slab of 2^side_slab_shift entries
     int side_slab_shift;
     int side_dense;      // 1: entries [0, side_n) (look-back pass); 0: per-tile slabs
-    u64 sub_n;           // side-buffer terms copied to the level-2 subset buffer
-    u32 done[4];         // last-workgroup counters, one per kernel kind
-    u32 flags;           // STS_F_* below
+    // fields updated with atomics sit on cache lines of their own: every
+    // workgroup of every kernel reads the fields around them, and reads of a
+    // line wait behind the atomics queued on it
+    alignas(128) u64 sub_n; // side-buffer terms copied to the level-2 subset buffer
+    alignas(128) u32 done[4]; // last-workgroup counters, one per kernel kind
+    alignas(128) u32 flags;   // STS_F_* below
     // truncation rule
-    u64 K;               // top-k (0 = off)
+    alignas(128) u64 K;  // top-k (0 = off)
     double p;            // p-mass (off unless 0 < p < 1)
     // decision
     int keep_all;        // the rule keeps every candidate
