@@ -436,8 +436,10 @@ def cpu_baseline(st, circuit, gi, K, p, sample_terms):
         "unit": "updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one gate step (apply + truncate) of the plain C oracle on {take} of the {n} steady-state "
-                  f"terms (random subset), K scaled to {kk}, p={p}, FP64",
+        "sample": (f"one gate step (apply + truncate) of the plain C oracle on the whole steady state "
+                   f"({n} terms), K={kk}, p={p}, FP64" if take == n else
+                   f"one gate step (apply + truncate) of the plain C oracle on {take} of the {n} steady-state "
+                   f"terms (random subset), K scaled to {kk}, p={p}, FP64"),
     }
 
 

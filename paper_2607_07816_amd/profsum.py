@@ -23,7 +23,7 @@ import sys
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 
-SHORT_NAMES = ("k_radix_pass", "k_radix_hist", "k_radix_scan", "k_tile_hist", "k_tile_extract", "k_tile_emit",
+SHORT_NAMES = ("k_radix_pass", "k_radix_count", "k_radix_hist", "k_radix_scan", "k_tile_hist", "k_tile_extract", "k_tile_emit",
                "k_tile_compact", "k_group_hist", "k_group_compact", "k_group_extract", "k_group_emit", "k_pick1",
                "k_side_hist", "k_side_extract", "k_final", "k_tile_kept", "k_tile_scan", "k_init_state",
                "k_set_n")
@@ -42,7 +42,8 @@ def short(name: str) -> str:
             if m and extra:
                 extra += f",m={m.group(1)}"
             return key + (f"<{extra}>" if extra else "")
-    return name.split("(")[0][:48]
+    name = name.replace("(anonymous namespace)::", "")
+    return name.split("(")[0][:48] or name[:48]
 
 
 def source_digest() -> str:
