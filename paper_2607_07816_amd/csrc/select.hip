@@ -40,8 +40,24 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     DevCtl *ctl = b.ctl;
     u64 *h1 = b.h1;
 
-    // own bins
-    u64 c[8];
+    // own bins: every load issued before any is used
+    u64 c[8], hi[8], lo[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int e = 2047 - 8 * t - k;
+        c[k] = h1[e];
+        hi[k] = h1[STS_NBIN + e];
+        lo[k] = h1[2 * STS_NBIN + e];
+    }
+    // the per-workgroup peaks too (reduced below)
+    constexpr int BPT = (STS_MAX_GROUPS + 255) / 256;
+    u64 bwv[BPT], bkv[BPT];
+#pragma unroll
+    for (int r = 0; r < BPT; ++r) {
+        const int i = t + 256 * r;
+        bwv[r] = i < groups ? b.best[i] : 0ull;
+        bkv[r] = i < groups ? b.best[STS_MAX_GROUPS + i] : ~0ull;
+    }
     u128 ms[8];
     Big chunk;
     big_zero(chunk);
@@ -49,8 +65,7 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int e = 2047 - 8 * t - k;
-        c[k] = h1[e];
-        ms[k] = ((u128)h1[STS_NBIN + e] << 26) + (u128)h1[2 * STS_NBIN + e];
+        ms[k] = ((u128)hi[k] << 26) + (u128)lo[k];
         ccount += c[k];
         if (c[k]) big_add_shifted(chunk, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
     }
@@ -106,8 +121,9 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     // peak: reduce the per-workgroup bests
     {
         u64 bw = 0, bk = ~0ull;
-        for (int i = t; i < groups; i += 256) {
-            const u64 w = b.best[i], k = b.best[STS_MAX_GROUPS + i];
+#pragma unroll
+        for (int r = 0; r < BPT; ++r) {
+            const u64 w = bwv[r], k = bkv[r];
             if (w > bw || (w == bw && k < bk)) {
                 bw = w;
                 bk = k;
@@ -782,23 +798,35 @@ __global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
 
 __global__ void __launch_bounds__(1024) k_tile_scan(PassBufs b)
 {
+    constexpr int CH = 8; // tiles per thread per round, loaded before use
     __shared__ u64 s_scratch[16];
+    __shared__ u64 s_carry;
     DevCtl *ctl = b.ctl;
     const u64 n = *b.n_in;
     const u64 ntiles = (n + 2047) / 2048;
-    const u64 per = (ntiles + 1023) / 1024;
-    const u64 lo = threadIdx.x * per;
-    const u64 hi = lo + per < ntiles ? lo + per : ntiles;
-    u64 sum = 0;
-    for (u64 t = lo; t < hi; ++t) sum += b.t_off[t];
-    u64 total;
-    u64 run = block_excl_scan<u64, 1024>(sum, s_scratch, &total);
-    for (u64 t = lo; t < hi; ++t) {
-        const u64 c = b.t_off[t];
-        b.t_off[t] = run;
-        run += c;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (u64 c0 = 0; c0 < ntiles; c0 += 1024ull * CH) {
+        const u64 lo = c0 + (u64)threadIdx.x * CH;
+        u64 v[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) v[k] = lo + k < ntiles ? b.t_off[lo + k] : 0ull;
+        u64 sum = 0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) sum += v[k];
+        u64 total;
+        u64 run = block_excl_scan<u64, 1024>(sum, s_scratch, &total) + s_carry;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            if (lo + k < ntiles) b.t_off[lo + k] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += total;
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
+        const u64 total = s_carry;
         *b.n_out = total;
         if (total > b.out_cap) atomicOr(&ctl->flags, STS_F_OUT_OVERFLOW);
     }
