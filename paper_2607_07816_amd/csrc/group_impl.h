@@ -643,10 +643,12 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
                     atomicAdd(&b.h1[STS_NBIN + e_], mant >> 26);
                     atomicAdd(&b.h1[2 * STS_NBIN + e_], mant & ((1ull << 26) - 1));
                 }
-                const u64 tagged = wb | (1ull << 63);
-                if (tagged > bw || (tagged == bw && key < bk)) {
-                    bw = tagged;
-                    bk = key;
+                if (M == 0) { // the peak is only asked of the state itself (sts_peak)
+                    const u64 tagged = wb | (1ull << 63);
+                    if (tagged > bw || (tagged == bw && key < bk)) {
+                        bw = tagged;
+                        bk = key;
+                    }
                 }
             }
             if (predict) {

@@ -118,8 +118,9 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         }
         s_hit = 0xffffffffu;
     }
-    // peak: reduce the per-workgroup bests
-    {
+    // peak: reduce the per-workgroup bests (written by the identity pass of
+    // sts_peak only)
+    if (peak_only) {
         u64 bw = 0, bk = ~0ull;
 #pragma unroll
         for (int r = 0; r < BPT; ++r) {
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         }
     }
     __syncthreads();
-    if (t == 0) {
+    if (peak_only && t == 0) {
         u64 w = s_bw[0], k = s_bk[0];
         for (int i = 1; i < 4; ++i)
             if (s_bw[i] > w || (s_bw[i] == w && s_bk[i] < k)) {
