@@ -787,14 +787,17 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(GateArg g, PassBufs b)
     __shared__ u32 s_out;
     const int tid = threadIdx.x;
     DevCtl *ctl = b.ctl;
+    const u64 tile = blockIdx.x; // below the tile arrays' length (the launch's bound)
+    // every control load issued before any is used
     const u64 n = *b.n_in;
-    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
-    const u64 tile = blockIdx.x;
-    if (tile >= ntiles) return;
-    const bool all = b.materialise || ctl->keep_all;
+    const int keep_all = ctl->keep_all, dropped = ctl->dropped;
     const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
-    const bool rescale = !all && ctl->dropped;
     const double scale = ctl->scale;
+    const u64 out0 = b.t_off[tile];
+    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
+    if (tile >= ntiles) return;
+    const bool all = b.materialise || keep_all;
+    const bool rescale = !all && dropped;
     const u64 *keys = b.keys;
     const AT *amps = (const AT *)b.amps;
     const u64 base = tile * TT_TG;
@@ -803,7 +806,6 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(GateArg g, PassBufs b)
     if (tid == 0) s_out = 0;
     stage_tile<AT, M>(s, g, keys, amps, lo, hi);
     __syncthreads();
-    const u64 out0 = b.t_off[tile];
 #pragma unroll 1
     for (int k = 0; k < TT_IT; ++k) {
         const u64 e = base + (u64)k * STS_WG + tid;

@@ -548,11 +548,15 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
 {
     constexpr int UN = 4;
     DevCtl *ctl = b.ctl;
-    if (ctl->keep_all || (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
-    if (ctl->sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
+    // every control load issued before any is used
+    const int keep_all = ctl->keep_all;
+    const u32 flags = ctl->flags;
+    const u64 sub_count = ctl->sub_count;
     const SideChunks sc = side_chunks(b, ctl);
     const int vshift = ctl->vshift;
     const u128 vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
+    if (keep_all || (flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
+    if (sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
     const u64 lt = sts_lanemask_lt();
     for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
         u64 cbase, count;
@@ -766,14 +770,15 @@ __global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
     constexpr int UN = 4;
     __shared__ u32 s_scratch[4];
     DevCtl *ctl = b.ctl;
+    const u64 tile = blockIdx.x; // below the tile arrays' length (the launch's bound)
+    // every control load issued before any is used
     const u64 n = *b.n_in;
-    const u64 ntiles = (n + 2047) / 2048;
-    const u64 tile = blockIdx.x;
-    if (tile >= ntiles) return;
     const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
     const int shift = ctl->side_slab_shift;
-    const u64 base = tile << shift;
     u64 ns = b.t_side[tile];
+    const u64 ntiles = (n + 2047) / 2048;
+    if (tile >= ntiles) return;
+    const u64 base = tile << shift;
     if (base >= b.side_cap) ns = 0;
     else if (ns > b.side_cap - base) ns = b.side_cap - base;
     u32 c = 0;
