@@ -38,7 +38,7 @@ u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
     u64 ctl, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
-        t_above, t_side, t_off, tctr, dU, total;
+        t_above, t_side, t_off, tctr, dU, sub_cnt, total;
 };
 
 // tiles of the LDS-tiled passes (2048 terms each) and the side-buffer entries:
@@ -79,6 +79,7 @@ Layout make_layout(u64 cap, int prec)
     L.t_off = take(ttiles * 8);
     L.tctr = take(16 * 4);
     L.dU = take(kULen * 8);
+    L.sub_cnt = take((STS_SUB_REGIONS + 1) * 128);
     L.total = o;
     return L;
 }
@@ -109,6 +110,7 @@ struct sts_ctx {
     u64 *t_off = nullptr;
     u32 *tctr = nullptr;
     double *dU = nullptr;
+    u32 *sub_cnt = nullptr;
     double *hU = nullptr;    // pinned staging of U for m >= 4
     hipEvent_t u_event = nullptr;
     bool u_event_live = false;
@@ -219,6 +221,7 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     b.sub_key = c->sub_key;
     b.sub_w = c->sub_w;
     b.sub_cap = STS_SUB_CAP;
+    b.sub_cnt = c->sub_cnt;
     if (out >= 0) {
         b.out_keys = c->keys[out];
         b.out_amps = c->amps[out];
@@ -454,6 +457,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     c->t_off = (u64 *)(c->mem + L.t_off);
     c->tctr = (u32 *)(c->mem + L.tctr);
     c->dU = (double *)(c->mem + L.dU);
+    c->sub_cnt = (u32 *)(c->mem + L.sub_cnt);
 
     hipError_t e = hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hU, kULen * sizeof(double), hipHostMallocDefault);

@@ -44,7 +44,6 @@ struct DevCtl {
     // fields updated with atomics sit on cache lines of their own: every
     // workgroup of every kernel reads the fields around them, and reads of a
     // line wait behind the atomics queued on it
-    alignas(128) u64 sub_n; // side-buffer terms copied to the level-2 subset buffer
     alignas(128) u32 done[4]; // last-workgroup counters, one per kernel kind
     alignas(128) u32 flags;   // STS_F_* below
     // truncation rule

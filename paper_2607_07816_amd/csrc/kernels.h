@@ -38,9 +38,11 @@ struct PassBufs {
     u64 *side_key;        // side buffer: candidates of the exponent holding the cut
     u64 *side_w;
     u64 side_cap;
-    u64 *sub_key;         // the level-2 subset of the side buffer
-    u64 *sub_w;
+    u64 *sub_key;         // the level-2 subset of the side buffer, in STS_SUB_REGIONS
+    u64 *sub_w;           // regions of sub_cap / STS_SUB_REGIONS entries
     u64 sub_cap;
+    u32 *sub_cnt;         // per region its fill count, 32 words (a cache line) apart; then an
+                          // overflow word at STS_SUB_REGIONS * 32
     u64 *out_keys;        // new state
     void *out_amps;
     u64 out_cap;
@@ -94,4 +96,5 @@ inline u64 sts_compact_groups(u64 n, int m)
 #define STS_GTILE (STS_WG * STS_GROUP_ITEMS)     // elements per compaction tile
 #define STS_MAX_GROUPS 2048                      // workgroups of a histogram pass (best-term slots)
 #define STS_SIDE_GROUPS 512
+#define STS_SUB_REGIONS 64                        // fill counters of the level-2 subset buffer
 #define STS_SUB_CAP (1u << 16)                   // level-2 subset buffer (terms)

@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
         if (threadIdx.x == 0) {
             sub_store(s_sub, ctl);
             ctl->level = 2;
-            ctl->sub_n = 0;
+            for (int i = 0; i <= STS_SUB_REGIONS; ++i) st_agent(&b.sub_cnt[i * 32], 0u);
         }
     } else if (threadIdx.x == 0) {
         atomicOr(&ctl->flags, STS_F_UNRESOLVED);
@@ -557,6 +557,12 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
     const u128 vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
     if (keep_all || (flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
     if (sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
+    // each wave fills one of STS_SUB_REGIONS regions, whose counters sit on
+    // separate cache lines (one shared counter would serialise every wave)
+    const u32 region = (blockIdx.x * 4u + (threadIdx.x >> 6)) % STS_SUB_REGIONS;
+    const u32 region_len = (u32)(b.sub_cap / STS_SUB_REGIONS);
+    const u64 region_base = (u64)region * region_len;
+    u32 *cnt = &b.sub_cnt[region * 32];
     const u64 lt = sts_lanemask_lt();
     for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
         u64 cbase, count;
@@ -586,12 +592,15 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
                 const u64 mask = __ballot(take);
                 if (!mask) continue;
                 const int leader = __ffsll((long long)mask) - 1;
-                u64 pos = 0;
-                if (sts_lane() == leader) pos = atomicAdd((unsigned long long *)&ctl->sub_n, (u64)__popcll(mask));
-                pos = __shfl(pos, leader, 64) + (u64)__popcll(mask & lt);
-                if (take && pos < b.sub_cap) {
-                    b.sub_key[pos] = k;
-                    b.sub_w[pos] = w[r];
+                u32 pos = 0;
+                if (sts_lane() == leader) {
+                    pos = atomicAdd(cnt, (u32)__popcll(mask));
+                    if (pos + (u32)__popcll(mask) > region_len) atomicOr(&b.sub_cnt[STS_SUB_REGIONS * 32], 1u);
+                }
+                pos = __shfl(pos, leader, 64) + (u32)__popcll(mask & lt);
+                if (take && pos < region_len) {
+                    b.sub_key[region_base + pos] = k;
+                    b.sub_w[region_base + pos] = w[r];
                 }
             }
         }
@@ -622,13 +631,40 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     if (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW)) return;
     const int t = threadIdx.x;
     const int e = ctl->e_star;
-    // the level-2 subset buffer when it holds the subset, else the side buffer
-    const bool small = ctl->sub_count <= b.sub_cap;
+    // the subset regions when they hold the whole subset, else the side buffer
+    // (entries of region r at r * region_len + [0, count_r); visited through
+    // an exclusive prefix of the counts, so only filled slots are read)
+    __shared__ u32 s_regpre[STS_SUB_REGIONS + 1];
+    const u32 region_len = (u32)(b.sub_cap / STS_SUB_REGIONS);
+    const bool small = ctl->sub_count <= b.sub_cap && ld_agent(&b.sub_cnt[STS_SUB_REGIONS * 32]) == 0u;
+    if (t < 64) { // one wave scans the region counts
+        static_assert(STS_SUB_REGIONS == 64, "one lane per region");
+        const u32 c0 = ld_agent(&b.sub_cnt[t * 32]);
+        const u32 c = c0 < region_len ? c0 : region_len;
+        const u32 inc = (u32)wave_incl_scan((u64)c);
+        s_regpre[t + 1] = inc;
+        if (t == 0) s_regpre[0] = 0;
+    }
+    __syncthreads();
     const u64 *src_w = small ? b.sub_w : b.side_w;
     const u64 *src_k = small ? b.sub_key : b.side_key;
-    SideView view = side_view(b, ctl);
-    if (small) view.dense = 1;
-    const u64 n = small ? ctl->sub_n : view.flat;
+    const SideView view = side_view(b, ctl);
+    const u64 n = small ? (u64)s_regpre[STS_SUB_REGIONS] : view.flat;
+    // physical index of visited entry f (false: an empty slot of the side buffer)
+    auto entry = [&](u64 f, u64 &i) -> bool {
+        if (small) {
+            int lo = 0, hi = STS_SUB_REGIONS; // region r with pre[r] <= f < pre[r + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_regpre[mid] <= f) lo = mid;
+                else hi = mid;
+            }
+            i = (u64)lo * region_len + (f - s_regpre[lo]);
+            return true;
+        }
+        i = f;
+        return side_valid(view, f);
+    };
     const u64 K = ctl->K;
     const u128 R = make128(ctl->R_lo, ctl->R_hi);
     if (t == 0) sub_load(s_sub, ctl);
@@ -641,8 +677,9 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         const u128 vpre = s_sub.vpre;
         for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
         __syncthreads();
-        for (u64 i = t; i < n; i += FT) {
-            if (!side_valid(view, i)) continue;
+        for (u64 f = t; f < n; f += FT) {
+            u64 i;
+            if (!entry(f, i)) continue;
             const u128 v = rank_key(src_w[i], src_k[i]);
             if ((v >> vshift) != vpre) continue;
             const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
@@ -663,8 +700,9 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     const u128 vpre = s_sub.vpre;
     if (t == 0) s_n = 0;
     __syncthreads();
-    for (u64 i = t; i < n; i += FT) {
-        if (!side_valid(view, i)) continue;
+    for (u64 f = t; f < n; f += FT) {
+        u64 i;
+        if (!entry(f, i)) continue;
         const u128 v = rank_key(src_w[i], src_k[i]);
         if ((v >> vshift) != vpre) continue;
         const u32 slot = atomicAdd(&s_n, 1u);
