@@ -535,7 +535,8 @@ template <int BITS> __device__ __forceinline__ u32 wave_claim_n(u32 cnt, u32 *co
 
 // LDS bins of the histogram pass: TT_NB exponent fields from TT_EBASE, in
 // TT_COPIES copies (lane % TT_COPIES picks one) so that lanes hitting the same
-// hot exponent do not all serialise on one address
+// hot exponent do not all serialise on one address; the copies of a bin are
+// adjacent, so they also fall in different LDS banks
 constexpr int TT_COPIES = 2;
 
 // add the LDS bins to the global exponent histogram and clear them
@@ -545,10 +546,10 @@ __device__ __forceinline__ void flush_bins(const PassBufs &b, u64 *s_hi, u64 *s_
         u64 hi = 0, lo = 0;
 #pragma unroll
         for (int c = 0; c < TT_COPIES; ++c) {
-            hi += s_hi[c * TT_NB + i];
-            lo += s_lo[c * TT_NB + i];
-            s_hi[c * TT_NB + i] = 0;
-            s_lo[c * TT_NB + i] = 0;
+            hi += s_hi[i * TT_COPIES + c];
+            lo += s_lo[i * TT_COPIES + c];
+            s_hi[i * TT_COPIES + c] = 0;
+            s_lo[i * TT_COPIES + c] = 0;
         }
         const u64 cnt = lo >> 44;
         if (cnt) {
@@ -589,7 +590,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
         ctl->side_ntiles = ntiles;
         ctl->side_slab_shift = 11 + M;
     }
-    const int copy = (int)(threadIdx.x % TT_COPIES) * TT_NB;
+    const int copy = (int)(threadIdx.x % TT_COPIES);
     u64 bw = 0, bk = ~0ull;
     int since_flush = 0;
     for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -636,8 +637,8 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
                 const u64 mant = sts_mant(wb);
                 const int bin = e_ - TT_EBASE;
                 if (bin >= 0 && bin < TT_NB) {
-                    atomicAdd(&s_hi[copy + bin], mant >> 26);
-                    atomicAdd(&s_lo[copy + bin], (mant & ((1ull << 26) - 1)) | (1ull << 44));
+                    atomicAdd(&s_hi[bin * TT_COPIES + copy], mant >> 26);
+                    atomicAdd(&s_lo[bin * TT_COPIES + copy], (mant & ((1ull << 26) - 1)) | (1ull << 44));
                 } else { // far outside the usual range: straight to the global bins
                     atomicAdd(&b.h1[e_], 1ull);
                     atomicAdd(&b.h1[STS_NBIN + e_], mant >> 26);
