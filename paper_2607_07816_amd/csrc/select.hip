@@ -33,6 +33,9 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
 {
     __shared__ Big s_big[256];
     __shared__ u64 s_cnt[256];
+    __shared__ u64 s_nz[4];
+    __shared__ Big s_tot;
+    __shared__ u64 s_totc;
     __shared__ Big s_T;
     __shared__ u32 s_hit;
     __shared__ u64 s_bw[4], s_bk[4];
@@ -69,31 +72,45 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         ccount += c[k];
         if (c[k]) big_add_shifted(chunk, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
     }
-    // inclusive scans (Hillis-Steele) of the chunk masses and counts
+    // prefixes in rank order. Only the few threads whose bins hold candidates
+    // matter (the others' prefixes equal their predecessor's), so one thread
+    // walks those in order: s_big / s_cnt become their exclusive prefixes, and
+    // s_tot / s_totc the totals.
     s_big[t] = chunk;
     s_cnt[t] = ccount;
+    const u64 nzmask = __ballot(ccount != 0);
+    if ((t & 63) == 0) s_nz[t >> 6] = nzmask;
     __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-        Big o;
-        u64 oc = 0;
-        const bool take = t >= d;
-        if (take) {
-            o = s_big[t - d];
-            oc = s_cnt[t - d];
-        }
-        __syncthreads();
-        if (take) {
-            big_add(chunk, o);
-            ccount += oc;
-            s_big[t] = chunk;
-            s_cnt[t] = ccount;
-        }
-        __syncthreads();
-    }
-    // chunk / ccount now inclusive; exclusive = inclusive - own
-    const u64 total_c = s_cnt[255];
     if (t == 0) {
-        Big W = s_big[255];
+        Big acc;
+        big_zero(acc);
+        u64 cacc = 0;
+        for (int w = 0; w < 4; ++w) {
+            u64 m = s_nz[w];
+            while (m) {
+                const int i = 64 * w + __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const Big own = s_big[i];
+                const u64 oc = s_cnt[i];
+                s_big[i] = acc;
+                s_cnt[i] = cacc;
+                big_add(acc, own);
+                cacc += oc;
+            }
+        }
+        s_tot = acc;
+        s_totc = cacc;
+    }
+    __syncthreads();
+    const bool nz = ccount != 0;
+    Big excl = s_big[t];       // meaningful where nz
+    const u64 cexcl = s_cnt[t];
+    big_add(chunk, excl);      // inclusive
+    ccount += cexcl;
+    // chunk / ccount now inclusive where nz
+    const u64 total_c = s_totc;
+    if (t == 0) {
+        Big W = s_tot;
         const double Wd = big_to_double(W);
         ctl->cand_all = total_c;
         if (peak_only) {
@@ -161,46 +178,43 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         return;
     }
 
-    // first bin (in rank order) where the rule is met
+    // first bin (in rank order) where the rule is met. Prefixes only grow in
+    // rank order, so it lies in the first thread whose inclusive prefix meets
+    // the rule; that thread alone walks its bins.
     const u64 K = ctl->K;
     const double p = ctl->p;
     const bool p_on = p > 0.0 && p < 1.0;
-    Big S = chunk; // exclusive prefix: inclusive minus own bins
-    u64 cnt = ccount;
-    {
-        Big own;
-        big_zero(own);
-        u64 oc = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int e = 2047 - 8 * t - k;
-            if (c[k]) big_add_shifted(own, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
-            oc += c[k];
-        }
-        big_sub(S, own);
-        cnt -= oc;
-    }
+    const bool t_hit = nz && ((K > 0 && ccount >= K) || (p_on && big_cmp(chunk, s_T) >= 0));
+    if (t_hit) atomicMin(&s_hit, (u32)t);
+    __syncthreads();
     u32 hit = 0xffffffffu;
     Big S_hit;
     u64 cnt_hit = 0;
+    if ((u32)t == s_hit) {
+        Big S = excl;
+        u64 cnt = cexcl;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (hit == 0xffffffffu && c[k]) {
-            const int e = 2047 - 8 * t - k;
-            Big inc = S;
-            big_add_shifted(inc, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
-            const bool hk = K > 0 && cnt + c[k] >= K;
-            const bool hp = p_on && big_cmp(inc, s_T) >= 0;
-            if (hk || hp) {
-                hit = (u32)(8 * t + k);
-                S_hit = S;
-                cnt_hit = cnt;
-            } else {
-                S = inc;
-                cnt += c[k];
+        for (int k = 0; k < 8; ++k) {
+            if (hit == 0xffffffffu && c[k]) {
+                const int e = 2047 - 8 * t - k;
+                Big inc = S;
+                big_add_shifted(inc, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
+                const bool hk = K > 0 && cnt + c[k] >= K;
+                const bool hp = p_on && big_cmp(inc, s_T) >= 0;
+                if (hk || hp) {
+                    hit = (u32)(8 * t + k);
+                    S_hit = S;
+                    cnt_hit = cnt;
+                } else {
+                    S = inc;
+                    cnt += c[k];
+                }
             }
         }
     }
+    __syncthreads();
+    if (t == 0) s_hit = 0xffffffffu;
+    __syncthreads();
     if (hit != 0xffffffffu) atomicMin(&s_hit, hit);
     __syncthreads();
     const u32 first = s_hit;
