@@ -317,6 +317,19 @@ __device__ __forceinline__ int sts_lane() { return __lane_id(); }
 
 __device__ __forceinline__ u64 sts_lanemask_lt() { return (1ull << sts_lane()) - 1ull; }
 
+// The workgroups of a launch are dealt to the XCDs in turn (workgroup b to
+// XCD b % 8), and each XCD has its own L2. sts_xcd_tile renumbers them so
+// that every XCD works through one contiguous range of tiles: neighbouring
+// tiles, whose output runs share cache lines, then meet in the same L2.
+// A bijection of [0, tiles) for tiles == gridDim.x.
+#define STS_XCDS 8
+__device__ __forceinline__ u32 sts_xcd_tile(u32 b, u32 tiles)
+{
+    const u32 x = b % STS_XCDS, i = b / STS_XCDS;
+    const u32 q = tiles / STS_XCDS, r = tiles % STS_XCDS;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // inclusive scan over the 64 lanes of a wave
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v)

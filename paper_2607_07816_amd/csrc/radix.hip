@@ -116,18 +116,21 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
-    for (int i = tid; i < NW * 256; i += STS_WG) (&s_cnt[0][0])[i] = 0;
+    const u64 n = *n_in;
+    const u64 tot_d = totals[tid];
+    if (blockIdx.x == 0 && tid == 0) *n_out = n;
+    // the launch may have more workgroups than the state has tiles; the
+    // state's tiles go to the XCDs in contiguous ranges
+    const u64 nt = (n + STS_TILE - 1) / STS_TILE;
+    if (blockIdx.x >= nt) return;
+    const u64 tile = sts_xcd_tile(blockIdx.x, nt < gridDim.x ? (u32)nt : gridDim.x);
     // global offset of this tile's first key of digit tid: the digit's base
     // (exclusive scan of the totals) plus the tiles before it; loaded now,
     // used after the ranking
-    const u64 tile = blockIdx.x;
-    const u64 tot_d = totals[tid];
     const u64 pre_d = prefix[(u64)tid * tiles_cap + tile];
+    for (int i = tid; i < NW * 256; i += STS_WG) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
-    const u64 n = *n_in;
-    if (tile == 0 && tid == 0) *n_out = n;
     const u64 base = tile * STS_TILE;
-    if (base >= n) return;
 
     // issue every key and amplitude load of the thread first
     u64 key[IT];
