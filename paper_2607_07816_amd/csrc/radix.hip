@@ -32,10 +32,14 @@ __global__ void __launch_bounds__(STS_WG) k_radix_count(const u64 *__restrict__ 
                                                          int shift, u32 *__restrict__ counts, u64 tiles_cap)
 {
     __shared__ u32 s_h[256];
+    const u64 n = *n_in;
+    // the state's tiles go to the XCDs in contiguous ranges, so that the
+    // counts of neighbouring tiles (adjacent in each digit's row) are written
+    // through one L2; workgroups past the state's tiles write zeros
+    const u64 nt = (n + STS_TILE - 1) / STS_TILE;
+    const u64 tile = blockIdx.x < nt ? sts_xcd_tile(blockIdx.x, nt < gridDim.x ? (u32)nt : gridDim.x) : blockIdx.x;
     s_h[threadIdx.x] = 0;
     __syncthreads();
-    const u64 n = *n_in;
-    const u64 tile = blockIdx.x;
     const u64 base = tile * STS_TILE;
     u64 kk[STS_TILE_ITEMS];
     if (base + STS_TILE <= n) {
