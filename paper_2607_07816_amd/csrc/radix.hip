@@ -99,16 +99,19 @@ __global__ void __launch_bounds__(STS_WG) k_radix_scan(const u32 *__restrict__ c
     if (threadIdx.x == 0) totals[d] = s_carry;
 }
 
-template <typename AT>
-__global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ kin, const AT *__restrict__ ain,
-                                                        u64 *__restrict__ kout, AT *__restrict__ aout,
+// An amplitude is moved as W plain 64-bit words (W = 1: complex64, W = 2:
+// complex128), held in one register array per word (an array of HIP's
+// 16-byte vector type would be left in scratch memory).
+template <int W>
+__global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ kin, const u64 *__restrict__ ain,
+                                                        u64 *__restrict__ kout, u64 *__restrict__ aout,
                                                         const u64 *n_in, u64 *n_out, u64 notmask, int shift,
                                                         const u64 *__restrict__ prefix,
                                                         const u64 *__restrict__ totals, u64 tiles_cap)
 {
     constexpr int NW = STS_WG / 64;
     constexpr int IT = STS_TILE_ITEMS;
-    constexpr int ESZ = sizeof(AT) > sizeof(u64) ? sizeof(AT) : sizeof(u64);
+    constexpr int ESZ = 8 * W;
     __shared__ u32 s_cnt[NW][256];
     __shared__ u32 s_dstart[256];
     __shared__ u64 s_base[256];
@@ -137,8 +140,7 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     const u64 base = tile * STS_TILE;
 
     // issue every key and amplitude load of the thread first
-    u64 key[IT];
-    AT amp[IT];
+    u64 key[IT], a0[IT], a1[IT];
     u32 dig[IT];
     u32 rank[IT];
     if (base + STS_TILE <= n) {
@@ -147,7 +149,8 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
         for (int k = 0; k < IT; ++k) {
             const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
             key[k] = kin[e];
-            amp[k] = ain[e];
+            a0[k] = ain[e * W];
+            if (W == 2) a1[k] = ain[e * W + 1];
         }
     } else {
 #pragma unroll
@@ -155,7 +158,8 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
             const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
             if (e < n) {
                 key[k] = kin[e];
-                amp[k] = ain[e];
+                a0[k] = ain[e * W];
+                if (W == 2) a1[k] = ain[e * W + 1];
             } else {
                 key[k] = 0ull;
             }
@@ -224,15 +228,20 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     __syncthreads();
 
     // same permutation for the amplitudes
-    AT *sa = reinterpret_cast<AT *>(s_buf);
+    u64 *sa = reinterpret_cast<u64 *>(s_buf);
 #pragma unroll
     for (int k = 0; k < IT; ++k) {
-        if (dig[k] < 256u) sa[pos[k]] = amp[k];
+        if (dig[k] < 256u) {
+            sa[pos[k] * W] = a0[k];
+            if (W == 2) sa[pos[k] * W + 1] = a1[k];
+        }
     }
     __syncthreads();
     for (u32 i = tid; i < count; i += STS_WG) {
         const u32 d = s_dig[i];
-        aout[s_base[d] + (i - s_dstart[d])] = sa[i];
+        const u64 o = (s_base[d] + (i - s_dstart[d])) * W;
+        aout[o] = sa[i * W];
+        if (W == 2) aout[o + 1] = sa[i * W + 1];
     }
 }
 
@@ -256,11 +265,12 @@ hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kou
                              u64 *n_out, u64 notmask, int shift, const u64 *prefix, const u64 *totals,
                              u64 tiles_cap, int tiles, hipStream_t s)
 {
+    static_assert(sizeof(double2) == 2 * sizeof(u64) && sizeof(float2) == sizeof(u64), "amplitude words");
     if (prec == 0)
-        hipLaunchKernelGGL(k_radix_pass<double2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const double2 *)ain,
-                           kout, (double2 *)aout, n_in, n_out, notmask, shift, prefix, totals, tiles_cap);
+        hipLaunchKernelGGL(k_radix_pass<2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const u64 *)ain, kout,
+                           (u64 *)aout, n_in, n_out, notmask, shift, prefix, totals, tiles_cap);
     else
-        hipLaunchKernelGGL(k_radix_pass<float2>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const float2 *)ain, kout,
-                           (float2 *)aout, n_in, n_out, notmask, shift, prefix, totals, tiles_cap);
+        hipLaunchKernelGGL(k_radix_pass<1>, dim3(tiles), dim3(STS_WG), 0, s, kin, (const u64 *)ain, kout,
+                           (u64 *)aout, n_in, n_out, notmask, shift, prefix, totals, tiles_cap);
     return hipGetLastError();
 }

@@ -486,7 +486,7 @@ __device__ __forceinline__ void side_flush(u64 *h2, u64 *s_hi, u64 *s_lo)
 
 __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
 {
-    constexpr int UN = 4; // entries in flight per thread
+    constexpr int UN = 16; // entries in flight per lane
     __shared__ u64 s_hi[STS_NBIN];
     __shared__ u64 s_lo[STS_NBIN];
     __shared__ u128 s_m[256];
@@ -501,22 +501,29 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
     }
     __syncthreads();
     const SideChunks sc = side_chunks(b, ctl);
+    // each wave takes a chunk of its own, so a workgroup has four chunks'
+    // loads in flight; a round of four chunks adds at most 4 * chunk_max
+    // entries, and the bins are flushed before they could overflow
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const u64 chunk_max = sc.dense ? 8192 : (1ull << sc.shift);
     u64 since = 0;
-    for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
-        u64 base, count;
-        chunk_range(sc, t, base, count);
-        if (since + count > SH_FLUSH) { // uniform across the workgroup
+    for (u64 r0 = (u64)blockIdx.x * 4; r0 < sc.nchunks; r0 += (u64)gridDim.x * 4) {
+        if (since + 4 * chunk_max > SH_FLUSH) { // uniform across the workgroup
             __syncthreads();
             side_flush(h2, s_hi, s_lo);
             __syncthreads();
             since = 0;
         }
-        since += count;
-        for (u64 i0 = 0; i0 < count; i0 += UN * 256) {
+        since += 4 * chunk_max;
+        const u64 t = r0 + wv;
+        if (t >= sc.nchunks) continue;
+        u64 base, count;
+        chunk_range(sc, t, base, count);
+        for (u64 i0 = 0; i0 < count; i0 += UN * 64) {
             u64 w[UN];
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
-                const u64 i = i0 + (u64)r * 256 + threadIdx.x;
+                const u64 i = i0 + (u64)r * 64 + lane;
                 w[r] = i < count ? b.side_w[base + i] : ~0ull;
             }
 #pragma unroll
