@@ -38,7 +38,10 @@ def short(name: str) -> str:
                 extra = "c64"
             elif "double" in name:
                 extra = "c128"
-            m = re.search(r"Li(\d)E", name)
+            elif key == "k_radix_pass":  # templated on 64-bit words per amplitude
+                w = re.search(r"k_radix_pass(?:<|ILi)(\d)", name)
+                extra = {"1": "c64", "2": "c128"}.get(w.group(1), "") if w else ""
+            m = re.search(r"Li(\d)E", name) if key != "k_radix_pass" else None
             if m and extra:
                 extra += f",m={m.group(1)}"
             return key + (f"<{extra}>" if extra else "")

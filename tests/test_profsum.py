@@ -49,3 +49,12 @@ def test_kernel_rows_steady_tail(tmp_path):
     (name, calls, tot, avg, lo, hi, steady), = rows
     assert name.startswith("k_tile_emit") and calls == 10
     assert avg == 5500 and steady == 8000 and lo == 1000 and hi == 10000
+
+
+def test_short_kernel_names():
+    from paper_2607_07816_amd.profsum import short
+    assert short("void (anonymous namespace)::k_radix_pass<1>(unsigned long const*)") == "k_radix_pass<c64>"
+    assert short("_ZN12_GLOBAL__N_112k_radix_passILi2EEEvPKyS2_PyS3_") == "k_radix_pass<c128>"
+    assert short("void sts_group::k_tile_hist<HIP_vector_type<float, 2u>, 2>(GateArg, PassBufs)") == "k_tile_hist<c64>"
+    assert short("void sts_group::k_tile_emit<HIP_vector_type<double, 2u>, 3>(GateArg, PassBufs)") == "k_tile_emit<c128>"
+    assert short("(anonymous namespace)::k_radix_count(unsigned long const*)") == "k_radix_count"
