@@ -9,6 +9,9 @@ exactly as it would alone; the batch only decides how many run at once
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
+import os
 import time
 from typing import Iterable, List, Optional, Sequence, Tuple
 
@@ -60,11 +63,46 @@ def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, pa
 DEFAULT_CANDIDATES = tuple((s, g) for s in (4, 8, 16, 32, 48) for g in (0, 16))
 
 
+def batch_signature(items, precision="c64") -> str:
+    """Key of a batch's shape for the autotuner's cache: the precision, the
+    number of circuits and a histogram of (qubits, log2 K, gates / 8, p on)
+    over them. Batches of the same mix of sizes share a configuration."""
+    hist = {}
+    for c, K, p in items:
+        k = (int(c.n), int(K).bit_length(), len(c.gates) // 8, bool(0.0 < p < 1.0))
+        hist[k] = hist.get(k, 0) + 1
+    body = json.dumps([precision, len(items), sorted([list(k) + [v] for k, v in hist.items()])])
+    return hashlib.sha256(body.encode()).hexdigest()[:32]
+
+
+def _load_cache(path):
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
 def autotune(items, precision="c64", sample: Optional[Sequence[int]] = None,
-             candidates: Iterable[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 1):
+             candidates: Iterable[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 1,
+             cache: Optional[str] = None):
     """Time each (streams, graph_steps) candidate on a sample of the batch
     and return (best config, {config: seconds}). The sample keeps the batch's
-    mix: by default every fourth circuit."""
+    mix: by default every fourth circuit.
+
+    With `cache` (a JSON file path), a batch whose signature (batch_signature)
+    and candidate list were tuned before returns the stored choice and
+    timings without running anything; a new result is added to the file.
+    The kernels' own shapes (tile sizes, items per thread, digit width) are
+    fixed at build time and are not tuned here."""
+    candidates = [tuple(int(x) for x in c) for c in candidates]
+    key = batch_signature(items, precision) + ":" + ",".join(f"{s}/{g}" for s, g in candidates)
+    if cache:
+        hit = _load_cache(cache).get(key)
+        if hit:
+            timings = {tuple(t[0]): float(t[1]) for t in hit["timings"]}
+            return tuple(hit["choice"]), timings
     idx = list(sample) if sample is not None else list(range(0, len(items), 4))
     sub = [items[i] for i in idx]
     packed = pack(sub)
@@ -76,4 +114,11 @@ def autotune(items, precision="c64", sample: Optional[Sequence[int]] = None,
             best = dt if best is None else min(best, dt)
         timings[cfg] = best
     choice = min(timings, key=timings.get)
+    if cache:
+        data = _load_cache(cache)
+        data[key] = {"choice": list(choice), "timings": [[list(k), v] for k, v in timings.items()]}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(data, fh, indent=1)
+        os.replace(tmp, cache)
     return choice, timings
