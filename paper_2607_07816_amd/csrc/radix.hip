@@ -62,41 +62,62 @@ __global__ void __launch_bounds__(STS_WG) k_radix_count(const u64 *__restrict__ 
 }
 
 // per digit (workgroup d): exclusive prefix of its tile counts, and its
-// total, both digit-major (coalesced; every load of a thread in flight at
-// once): prefix[d * tiles_cap + tile].
+// total, both digit-major: prefix[d * tiles_cap + tile]. A chunk of
+// STS_WG * CH counts is loaded and stored coalesced (lane-consecutive) and
+// transposed through LDS, so that each thread scans CH consecutive counts
+// (LDS rows padded against bank conflicts).
 __global__ void __launch_bounds__(STS_WG) k_radix_scan(const u32 *__restrict__ counts, u64 *__restrict__ prefix,
                                                         u64 *__restrict__ totals, const u64 *n_in, u64 tiles_cap)
 {
     constexpr int CH = 16;
+    constexpr int CHUNK = STS_WG * CH;
+    __shared__ u32 s_c[CHUNK + CHUNK / 32];
+    __shared__ u64 s_p[CHUNK + CHUNK / 16];
     __shared__ u64 scratch[STS_WG / 64];
     __shared__ u64 s_carry;
+    auto pc = [](u32 i) { return i + (i >> 5); }; // padded index into s_c
+    auto pp = [](u32 i) { return i + (i >> 4); }; // padded index into s_p
     const u64 n = *n_in;
     const u64 ntiles = (n + STS_TILE - 1) / STS_TILE;
     const u64 d = blockIdx.x;
+    const u32 t = threadIdx.x;
     const u32 *c = counts + d * tiles_cap;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    // chunks of STS_WG * CH tiles: thread t owns tiles [t*CH, t*CH+CH) of a chunk
-    for (u64 c0 = 0; c0 < ntiles; c0 += (u64)STS_WG * CH) {
-        const u64 lo = c0 + (u64)threadIdx.x * CH;
+    u64 *pr = prefix + d * tiles_cap;
+    if (t == 0) s_carry = 0;
+    for (u64 c0 = 0; c0 < ntiles; c0 += CHUNK) {
         u32 v[CH];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) v[k] = lo + k < ntiles ? c[lo + k] : 0u;
+        for (int k = 0; k < CH; ++k) {
+            const u64 i = c0 + (u64)k * STS_WG + t;
+            v[k] = i < ntiles ? c[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) s_c[pc((u32)k * STS_WG + t)] = v[k];
+        __syncthreads();
+        u32 mine[CH];
         u64 sum = 0;
 #pragma unroll
-        for (int k = 0; k < CH; ++k) sum += v[k];
+        for (int k = 0; k < CH; ++k) {
+            mine[k] = s_c[pc(t * CH + (u32)k)];
+            sum += mine[k];
+        }
         u64 total;
         u64 run = block_excl_scan<u64, STS_WG>(sum, scratch, &total) + s_carry;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
-            if (lo + k < ntiles) prefix[d * tiles_cap + lo + k] = run;
-            run += v[k];
+            s_p[pp(t * CH + (u32)k)] = run;
+            run += mine[k];
         }
         __syncthreads();
-        if (threadIdx.x == 0) s_carry += total;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const u64 i = c0 + (u64)k * STS_WG + t;
+            if (i < ntiles) pr[i] = s_p[pp((u32)k * STS_WG + t)];
+        }
+        if (t == 0) s_carry += total;
         __syncthreads();
     }
-    if (threadIdx.x == 0) totals[d] = s_carry;
+    if (t == 0) totals[d] = s_carry;
 }
 
 // An amplitude is moved as W plain 64-bit words (W = 1: complex64, W = 2:
