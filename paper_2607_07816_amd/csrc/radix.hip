@@ -160,7 +160,10 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
     __syncthreads();
     const u64 base = tile * STS_TILE;
 
-    // issue every key and amplitude load of the thread first
+    // issue every key and amplitude load of the thread first. The pass
+    // reads its input once, and the next pass (or the gate passes) reads its
+    // output: the loads are non-temporal, so the caches keep the output just
+    // written rather than the input
     u64 key[IT], a0[IT], a1[IT];
     u32 dig[IT];
     u32 rank[IT];
@@ -169,18 +172,18 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
-            key[k] = kin[e];
-            a0[k] = ain[e * W];
-            if (W == 2) a1[k] = ain[e * W + 1];
+            key[k] = __builtin_nontemporal_load(&kin[e]);
+            a0[k] = __builtin_nontemporal_load(&ain[e * W]);
+            if (W == 2) a1[k] = __builtin_nontemporal_load(&ain[e * W + 1]);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
             const u64 e = base + (u64)w * (64 * IT) + (u64)k * 64 + lane;
             if (e < n) {
-                key[k] = kin[e];
-                a0[k] = ain[e * W];
-                if (W == 2) a1[k] = ain[e * W + 1];
+                key[k] = __builtin_nontemporal_load(&kin[e]);
+                a0[k] = __builtin_nontemporal_load(&ain[e * W]);
+                if (W == 2) a1[k] = __builtin_nontemporal_load(&ain[e * W + 1]);
             } else {
                 key[k] = 0ull;
             }
