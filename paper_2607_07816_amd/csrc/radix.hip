@@ -18,6 +18,10 @@
 //                   of the totals, done in the workgroup), stage the tile in
 //                   LDS in digit order and write keys and amplitudes out in
 //                   coalesced runs.
+// The counting and scatter workgroups take the tiles in one contiguous range
+// per XCD (neighbouring tiles' output runs share cache lines, merged in that
+// XCD's L2), and the scatter's input loads are non-temporal (the cache keeps
+// the output, which the next pass reads).
 #include "kernels.h"
 
 namespace {
