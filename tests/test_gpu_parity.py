@@ -108,6 +108,10 @@ CASES = [
     (48, 4000, 5, 0, 0.5),
     (20, 1500, 2, 10 ** 6, 0.0),   # K above the candidate count: no-op
     (20, 1500, 2, 1, 0.0),         # K = 1
+    # 19 full 4096-term radix tiles and a ragged one (more tiles than XCDs,
+    # not a multiple of 8): the per-XCD tile ranges have a remainder
+    (40, 19 * 4096 + 1234, 2, 30000, 0.95),
+    (48, 70001, 1, 0, 0.9),
 ]
 
 
