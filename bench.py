@@ -84,8 +84,8 @@ def log(msg: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
-              "(sharding by global key bits), not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the state by global "
+              "key bits over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
