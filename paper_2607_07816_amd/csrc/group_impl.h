@@ -466,11 +466,28 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     const u64 rest = key & nm;
     const u32 b = s.bkt[li];
     const int sh = 64 - g.hb;
+    const int last = (int)(hi - lo);
+    // both nearest neighbours read at once (most runs end there), the rest of
+    // a run one step at a time
+    const bool hp = li > 0, hn = li + 1 < last;
+    u32 bp = 0, bn = 0;
+    u64 kp = 0, kn = 0;
+    if (hp) {
+        bp = s.bkt[li - 1];
+        kp = s.key[li - 1];
+    }
+    if (hn) {
+        bn = s.bkt[li + 1];
+        kn = s.key[li + 1];
+    }
     // backward: does an earlier member of this group lead it?
     int p = li - 1;
-    for (; p >= 0; --p) {
-        if (s.bkt[p] != b) break;
-        if ((s.key[p] & nm) == rest) return;
+    if (hp && bp == b) {
+        if ((kp & nm) == rest) return;
+        for (p = li - 2; p >= 0; --p) {
+            if (s.bkt[p] != b) break;
+            if ((s.key[p] & nm) == rest) return;
+        }
     }
     if (p < 0 && lo > 0) { // the run goes on below the staged range
         for (u64 q = lo; q > 0; --q) {
@@ -483,12 +500,14 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     group_clear<AT, M>(G);
     group_set<AT, M>(G, extract_bits<M>(key, g), amp);
     // forward: collect the other members
-    const int last = (int)(hi - lo);
     int f = li + 1;
-    for (; f < last; ++f) {
-        if (s.bkt[f] != b) break;
-        const u64 kf = s.key[f];
-        if ((kf & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kf, g), amps[lo + f]);
+    if (hn && bn == b) {
+        if ((kn & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kn, g), amps[lo + li + 1]);
+        for (f = li + 2; f < last; ++f) {
+            if (s.bkt[f] != b) break;
+            const u64 kf = s.key[f];
+            if ((kf & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kf, g), amps[lo + f]);
+        }
     }
     if (f == last) { // the run goes on above the staged range
         for (u64 q = hi; q < n; ++q) {
