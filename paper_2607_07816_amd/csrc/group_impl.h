@@ -467,26 +467,38 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     const u32 b = s.bkt[li];
     const int sh = 64 - g.hb;
     const int last = (int)(hi - lo);
-    // both nearest neighbours read at once (most runs end there), the rest of
-    // a run one step at a time
-    const bool hp = li > 0, hn = li + 1 < last;
-    u32 bp = 0, bn = 0;
-    u64 kp = 0, kn = 0;
+    // the two nearest neighbours on each side read at once (most runs end
+    // there), the rest of a run one step at a time
+    const bool hp = li > 0, hp2 = li > 1, hn = li + 1 < last, hn2 = li + 2 < last;
+    u32 bp = 0, bp2 = 0, bn = 0, bn2 = 0;
+    u64 kp = 0, kp2 = 0, kn = 0, kn2 = 0;
     if (hp) {
         bp = s.bkt[li - 1];
         kp = s.key[li - 1];
+    }
+    if (hp2) {
+        bp2 = s.bkt[li - 2];
+        kp2 = s.key[li - 2];
     }
     if (hn) {
         bn = s.bkt[li + 1];
         kn = s.key[li + 1];
     }
+    if (hn2) {
+        bn2 = s.bkt[li + 2];
+        kn2 = s.key[li + 2];
+    }
     // backward: does an earlier member of this group lead it?
     int p = li - 1;
     if (hp && bp == b) {
         if ((kp & nm) == rest) return;
-        for (p = li - 2; p >= 0; --p) {
-            if (s.bkt[p] != b) break;
-            if ((s.key[p] & nm) == rest) return;
+        p = li - 2;
+        if (hp2 && bp2 == b) {
+            if ((kp2 & nm) == rest) return;
+            for (p = li - 3; p >= 0; --p) {
+                if (s.bkt[p] != b) break;
+                if ((s.key[p] & nm) == rest) return;
+            }
         }
     }
     if (p < 0 && lo > 0) { // the run goes on below the staged range
@@ -503,10 +515,14 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     int f = li + 1;
     if (hn && bn == b) {
         if ((kn & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kn, g), amps[lo + li + 1]);
-        for (f = li + 2; f < last; ++f) {
-            if (s.bkt[f] != b) break;
-            const u64 kf = s.key[f];
-            if ((kf & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kf, g), amps[lo + f]);
+        f = li + 2;
+        if (hn2 && bn2 == b) {
+            if ((kn2 & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kn2, g), amps[lo + li + 2]);
+            for (f = li + 3; f < last; ++f) {
+                if (s.bkt[f] != b) break;
+                const u64 kf = s.key[f];
+                if ((kf & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kf, g), amps[lo + f]);
+            }
         }
     }
     if (f == last) { // the run goes on above the staged range
