@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=300, help="timed gate steps")
     ap.add_argument("--warmup", type=int, default=30, help="untimed gate steps before timing")
     ap.add_argument("--profile-steps", type=int, default=60, help="gate steps timed per kernel")
+    ap.add_argument("--precision", choices=["c64", "c128"], default=None,
+                    help="amplitude precision of the 48q/24q workloads (default: the workload's, complex64)")
     ap.add_argument("--workload", default="48q", choices=["48q", "24q", "c4", "c5"],
                     help="48q: the 48-qubit circuit (default); 24q: a 24-qubit one; c4: 256 uneven circuits, "
                          "batched against the plain one-at-a-time loop; c5: Poisson arrivals served with "
@@ -104,6 +106,8 @@ def main():
     else:
         circuit, cfg = C.workload_24q()
         prec = "c64"
+    if args.precision:
+        prec = args.precision
     K, p = cfg["K"], cfg["p"]
     if args.fuse:
         from paper_2607_07816_amd import compile as CC
@@ -186,7 +190,10 @@ def main():
                                       for k, v in sorted(kt.items(), key=lambda kv: -kv[1][0])))
     log(f"dominant {dom}: {avg_s * 1e6:.1f} us/launch, {per_launch / 1e6:.1f} MB/launch, {achieved:.0f} GB/s")
 
-    traffic_gbs = measured_traffic(dom, avg_s)
+    # counter summaries exist for the headline configuration only (unfused
+    # 48-qubit circuit, the precision in the file name)
+    profile_tag = f"peaked48_K2e24_{prec}" if args.workload == "48q" and not args.fuse else None
+    traffic_gbs = measured_traffic(dom, avg_s, profile_tag)
 
     key, prob = st.peak()
     log(f"state peak {key:#x} prob {prob:.4f} (hidden {circuit.hidden:#x})")
@@ -390,14 +397,17 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
-def measured_traffic(kind: str, avg_s: float):
-    """HBM bytes per launch of `kind` from the committed counter summary,
-    over the live average launch time (GB/s); None if there is no summary for
-    that kernel or the library's kernels changed since it was taken."""
+def measured_traffic(kind: str, avg_s: float, tag):
+    """HBM bytes per launch of `kind` from the committed counter summary of
+    the configuration `tag`, over the live average launch time (GB/s); None
+    if there is no summary for that kernel and configuration or the
+    library's kernels changed since it was taken."""
     from paper_2607_07816_amd import profsum
 
+    if tag is None:
+        return None
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        f"{kind}_peaked48_K2e24_c64_hbm_traffic.txt")
+                        f"{kind}_{tag}_hbm_traffic.txt")
     if not os.path.exists(path) or avg_s <= 0:
         return None
     rec = profsum.read_traffic(path)
