@@ -149,6 +149,27 @@ def test_ties_keep_smallest_keys(S):
         assert np.array_equal(kg, np.arange(K, dtype=np.uint64))
 
 
+def test_ties_beyond_the_subset_buffer(S):
+    # 2^18 bitwise-equal weights: the level-2 subset (every candidate) exceeds
+    # the subset buffer, so the last levels walk the side buffer itself and
+    # split the ties by key bits; the K smallest keys are kept, each with
+    # amplitude 1 / sqrt(K)
+    n = 18
+    keys = np.zeros(1, dtype=np.uint64)
+    amps = np.ones(1, dtype=np.complex128)
+    for K in (100000, 150001):
+        with S.State(n, K=K, precision="c128", capacity=1 << 19) as st:
+            st.load_terms(keys, amps)
+            for q in range(n):
+                st.apply_gate((q,), C.H_GATE)
+                if q == n - 1:
+                    st.truncate()
+            kg, ag = st.read_terms()
+        say(f"ties beyond the subset buffer K={K}")
+        assert np.array_equal(kg, np.arange(K, dtype=np.uint64))
+        assert np.abs(ag - 1.0 / np.sqrt(K)).max() <= 1e-12
+
+
 def test_pmass_exact_boundary(S):
     # 40 equal weights: the p = 0.5 cut reaches the target exactly at 20 terms
     keys = np.arange(40, dtype=np.uint64) * np.uint64(3)
