@@ -50,9 +50,13 @@
  *     allocated by the library.
  *   - A context is not thread-safe; distinct contexts may run concurrently
  *     on distinct streams.
- *   - STS_E_ARG and STS_E_CAPACITY leave the state as it was. STS_E_HIP
- *     and STS_E_NOMEM during a computation poison the context: afterwards
- *     only sts_free is valid (other calls return STS_E_STATE).
+ *   - STS_E_ARG and STS_E_CAPACITY leave the state as it was, with one
+ *     exception: a truncation whose cut exponent holds more candidates than
+ *     the side buffer (possible only for untiled 4- and 5-qubit gates on a
+ *     state near cap_terms) reports STS_E_CAPACITY from the device and
+ *     poisons the context. STS_E_HIP and STS_E_NOMEM during a computation
+ *     poison the context too: afterwards only sts_free is valid (other calls
+ *     return STS_E_STATE).
  */
 #ifndef STS_H
 #define STS_H
