@@ -305,6 +305,41 @@ def test_argument_errors(S):
         assert st.peak() == (0, 1.0)
 
 
+def test_capacity_errors_leave_the_state(S):
+    rng = np.random.default_rng(77)
+    keys, amps = random_state(rng, 20, 600)
+    order = np.argsort(keys)
+    keys, amps = keys[order], amps[order]
+    U = C.haar_unitary(rng, 2)
+
+    def same_state(st):
+        k, a = st.read_terms()
+        o = np.argsort(k)
+        assert np.array_equal(k[o], keys)
+        assert np.array_equal(a[o].view(np.uint64), amps.view(np.uint64))
+
+    # the un-truncated result of a gate (about 1200 terms) exceeds the
+    # capacity: the call that needs it drops that gate
+    with S.State(20, K=0, p=0.0, precision="c128", capacity=1024) as st:
+        st.load_terms(keys, amps)
+        st.apply_gate((3,), U)
+        with pytest.raises(S.CapacityError):
+            st.apply_gate((5,), U)
+        say("capacity: dropped gate")
+        same_state(st)
+        st.apply_gate((5,), np.eye(2))  # the context stays usable
+        st.truncate()
+        same_state(st)
+    # p-mass alone keeps more terms than the capacity holds
+    with S.State(20, K=0, p=0.999, precision="c128", capacity=1024) as st:
+        st.load_terms(keys, amps)
+        st.apply_gate((3,), U)
+        with pytest.raises(S.CapacityError):
+            st.truncate()
+        say("capacity: p-mass cut")
+        same_state(st)
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("cap_factor", [1, 4])
 def test_four_qubit_gate_tiled_and_untiled(S, prec, cap_factor):
