@@ -7,6 +7,10 @@
         HBM bytes per launch of one kernel from FETCH_SIZE and WRITE_SIZE,
         each scaled by what the same counter reads for a device-to-device
         copy of B bytes in the same run
+    python -m paper_2607_07816_amd.profsum counters DB [DB ...] --kernel PREFIX
+                                           --command "..." [--command "..."]
+        every collected counter per steady dispatch (and per wave) of the
+        named kernels, one --pmc pass per database
 
 Measurement tooling only: nothing here runs on the simulation path.
 """
@@ -161,6 +165,33 @@ def cmd_traffic(args):
     print("\n".join(out))
 
 
+def cmd_counters(args):
+    """Mean per steady dispatch of every counter in the given databases (one
+    rocprofv3 --pmc pass each), for the kernels named by prefix; per wave
+    too where SQ_WAVES was collected."""
+    vals = collections.defaultdict(dict)
+    for db in args.db:
+        cur = _db(db).cursor()
+        for (c,) in cur.execute("select distinct counter_name from counters_collection").fetchall():
+            for k, (v, n) in counter_means(db, c).items():
+                vals[k][c] = (v, n)
+    kernels = [k for k in sorted(vals) if any(k.startswith(p) for p in args.kernel)]
+    if not kernels:
+        raise SystemExit(f"none of {args.kernel} in {sorted(vals)}")
+    out = ["# rocprofv3 counters per dispatch (mean over each kernel's largest-grid dispatches)"]
+    for i, cmd in enumerate(args.command):
+        out.append(f"# command {i + 1}: {cmd}")
+    out.append(f"# library source digest: {source_digest()}")
+    for k in kernels:
+        waves = vals[k].get("SQ_WAVES", (0.0, 0))[0]
+        out.append(f"{k}  (dispatches: {max(n for _, n in vals[k].values())})")
+        for c in sorted(vals[k]):
+            v = vals[k][c][0]
+            per_wave = f"{v / waves:14.1f} per wave" if waves and c != "SQ_WAVES" else ""
+            out.append(f"  {c:28s} {v:16.4g} {per_wave}")
+    print("\n".join(out))
+
+
 def read_traffic(path: str):
     """Parse a traffic summary: {field: value} of its `name: value` lines."""
     out = {}
@@ -188,8 +219,12 @@ def main(argv=None):
     c.add_argument("--command", default="")
     c.add_argument("--command-fetch", default="")
     c.add_argument("--command-write", default="")
+    q = sub.add_parser("counters")
+    q.add_argument("db", nargs="+")
+    q.add_argument("--kernel", action="append", required=True, help="kernel name prefix (repeatable)")
+    q.add_argument("--command", action="append", default=[], help="command of each pass (repeatable)")
     args = ap.parse_args(argv)
-    {"trace": cmd_trace, "traffic": cmd_traffic}[args.mode](args)
+    {"trace": cmd_trace, "traffic": cmd_traffic, "counters": cmd_counters}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -58,3 +58,19 @@ def test_short_kernel_names():
     assert short("void sts_group::k_tile_hist<HIP_vector_type<float, 2u>, 2>(GateArg, PassBufs)") == "k_tile_hist<c64>"
     assert short("void sts_group::k_tile_emit<HIP_vector_type<double, 2u>, 3>(GateArg, PassBufs)") == "k_tile_emit<c128>"
     assert short("(anonymous namespace)::k_radix_count(unsigned long const*)") == "k_radix_count"
+
+
+def test_counters_per_dispatch_and_wave(tmp_path, capsys):
+    a = tmp_path / "a_results.db"
+    b = tmp_path / "b_results.db"
+    kern = "void sts_group::k_tile_emit<HIP_vector_type<float, 2u>, 2>(GateArg, PassBufs)"
+    other = "k_pick1(PassBufs, int, int, int)"
+    _make_db(a, "SQ_WAVES", [(1, kern, 100, [4.0]), (2, kern, 800, [16.0, 16.0]), (3, other, 256, [4.0])])
+    _make_db(b, "SQ_INSTS_VALU", [(1, kern, 100, [9.0]), (2, kern, 800, [3200.0]), (3, other, 256, [1.0])])
+    profsum.main(["counters", str(a), str(b), "--kernel", "k_tile_emit", "--command", "x", "--command", "y"])
+    out = capsys.readouterr().out
+    assert "k_tile_emit<c64>" in out and "k_pick1" not in out
+    line = [l for l in out.splitlines() if "SQ_INSTS_VALU" in l][0]
+    # steady dispatch only (grid 800): 3200 instructions over 32 waves
+    assert "3200" in line and "100.0 per wave" in line
+    assert "# command 2: y" in out
