@@ -6,8 +6,10 @@ outside the gate, apply the gate with the collision merge, rank, cut (p-mass
 then top-k), renormalise and write the survivors. The default workload is the
 48-qubit peaked circuit (16 + 16 layers of 24 Haar SU(4) on random qubit
 pairs, eps = 0.01, complex64 amplitudes), cut to min(K = 2^24, L_0.99) after
-every SU(4) step. Warm-up steps bring the state to its steady size (2^24
-terms); the timed steps then continue the same circuit.
+every SU(4) step. Warm-up runs at least --warmup steps and then continues
+until the state stops growing (2^24 terms on the default workload), so every
+timed step processes the steady-state term count; the timed steps then
+continue the same circuit.
 
 metric: gate-term updates/s = (input terms of the timed steps) / time.
 roofline: the kernel kind with the largest share of the step time, its
@@ -17,8 +19,12 @@ rocprofv3's FETCH_SIZE and WRITE_SIZE counters recorded for that kernel
 (copy-calibrated, read from the committed summary under profiles/) over the
 same average launch time, in GB/s; null when the summary was taken on other
 kernels than the ones built.
-cpu_baseline: the C oracle (one thread) on one gate step of a bounded sample
-of the steady-state GPU state.
+cpu_baseline: the C oracle on one gate step of the steady-state GPU state,
+on all host cores (its OpenMP twin, bitwise the same result) and on one core
+(the plain oracle), with the host CPU named.
+
+--workload copy measures the streaming ceiling of this GPU: device-to-device
+copies and an elementwise scale of 1 GiB, timed with HIP events.
 """
 from __future__ import annotations
 
@@ -62,10 +68,12 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=60, help="gate steps timed per kernel")
     ap.add_argument("--precision", choices=["c64", "c128"], default=None,
                     help="amplitude precision of the 48q/24q workloads (default: the workload's, complex64)")
-    ap.add_argument("--workload", default="48q", choices=["48q", "24q", "c4", "c5"],
+    ap.add_argument("--workload", default="48q", choices=["48q", "24q", "c4", "c5", "copy"],
                     help="48q: the 48-qubit circuit (default); 24q: a 24-qubit one; c4: 256 uneven circuits, "
                          "batched against the plain one-at-a-time loop; c5: Poisson arrivals served with "
-                         "continuous batching against the plain loop")
+                         "continuous batching against the plain loop; copy: the device's streaming ceiling")
+    ap.add_argument("--max-warmup", type=int, default=200,
+                    help="most warm-up steps spent waiting for the state to reach its steady size")
     ap.add_argument("--requests", type=int, default=48, help="requests of the c5 workload")
     ap.add_argument("--load", type=float, default=0.7, help="c5 offered load, as a fraction of served capacity")
     ap.add_argument("--batch", type=int, default=256, help="circuits of the c4 workload")
@@ -100,6 +108,8 @@ def main():
         return bench_batch(args)
     if args.workload == "c5":
         return bench_serve(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     if args.workload == "48q":
         circuit, cfg = C.workload_48q()
         prec = cfg["precision"]
@@ -116,9 +126,9 @@ def main():
         log(f"fused {ng} gates into {len(circuit.gates)} blocks of <= {args.fuse} qubits")
     amp_bytes = 8 if prec == "c64" else 16
     steps_avail = [i for i, t in enumerate(circuit.truncate_after) if t]
-    need = args.warmup + args.steps + args.profile_steps + 1
+    need = max(args.warmup, args.max_warmup) + args.steps + args.profile_steps + 1
     if need > len(steps_avail):
-        raise SystemExit(f"the circuit has {len(steps_avail)} truncated steps; asked for {need}")
+        raise SystemExit(f"the circuit has {len(steps_avail)} truncated steps; asked for up to {need}")
 
     torch.cuda.init()
     dev = torch.cuda.current_device()
@@ -147,10 +157,23 @@ def main():
                 done += 1
             gi += 1
 
+    # warm-up: at least --warmup steps, then on until the state stops
+    # growing (it holds K terms, or the p-mass cut keeps it below K), so that
+    # every timed step is a steady-state step
     t_w = time.perf_counter()
     run(args.warmup)
+    warm = args.warmup
+    full = min(K, 1 << circuit.n) if K else 1 << min(circuit.n, 62)
+    n_now, flat = st.num_terms(), 0
+    while n_now < full and flat < 5 and warm < args.max_warmup:
+        run(1)
+        warm += 1
+        n_next = st.num_terms()
+        flat = flat + 1 if n_next <= n_now else 0
+        n_now = n_next
     torch.cuda.synchronize()
-    log(f"warm-up {args.warmup} steps in {time.perf_counter() - t_w:.2f}s; terms {st.num_terms()}")
+    log(f"warm-up {warm} steps (at least {args.warmup} asked) in {time.perf_counter() - t_w:.2f}s; "
+        f"terms {n_now} of {full}")
 
     # timed region
     c0 = st.counters()
@@ -161,9 +184,12 @@ def main():
     t1 = time.perf_counter()
     c1 = st.counters()
     updates = c1["term_updates"] - c0["term_updates"]
+    timed_steps = c1["gate_steps"] - c0["gate_steps"]
+    timed_cand = c1["candidates"] - c0["candidates"]
     elapsed = t1 - t0
     value = updates / elapsed
-    log(f"timed {args.steps} steps: {elapsed:.3f}s, {updates} updates, {value:.3e} updates/s")
+    log(f"timed {timed_steps} steps: {elapsed:.3f}s, {updates} updates ({updates / max(timed_steps, 1):.0f} "
+        f"per step), {value:.3e} updates/s")
 
     # per-kernel timing over further steps (HIP events on the library's stream)
     st.profile(True)
@@ -174,6 +200,7 @@ def main():
     c3 = st.counters()
     st.profile(False)
     nsteps = c3["gate_steps"] - c2["gate_steps"]
+    # per-launch units of the roofline: the profiled steps' own averages
     n_in = (c3["term_updates"] - c2["term_updates"]) / max(nsteps, 1)
     n_cand = (c3["candidates"] - c2["candidates"]) / max(nsteps, 1)
     n_out = min(n_in, K)
@@ -210,7 +237,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": elapsed / max(timed_steps, 1) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -222,8 +249,9 @@ def main():
             "n_qubits": circuit.n,
             "K": K,
             "p": p,
-            "terms_per_step": n_in,
-            "candidates_per_step": n_cand,
+            "warmup_steps_run": warm,
+            "terms_per_step": updates / max(timed_steps, 1),
+            "candidates_per_step": timed_cand / max(timed_steps, 1),
         },
         "roofline": {
             "bound": "hbm",
@@ -233,6 +261,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic_gbs,
+            "launch_terms": n_in,
+            "launches_timed": dom_n,
             "step_algorithmic_GBps": step_bytes / (total_ms / max(nsteps, 1) / 1e3) / 1e9 if total_ms else None,
         },
         "cpu_baseline": cpu,
@@ -419,8 +449,22 @@ def measured_traffic(kind: str, avg_s: float, tag):
     return tb / avg_s / 1e9
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(st, circuit, gi, K, p, sample_terms):
-    """Time the C oracle on one gate step of a sample of the GPU's state."""
+    """Time the C oracle on one gate step of (a sample of) the GPU's state:
+    on all the host cores this process may use (the oracle's OpenMP twin)
+    and on one core (the plain oracle); both must give the same terms."""
     import numpy as np
 
     from oracle import c_oracle
@@ -437,20 +481,68 @@ def cpu_baseline(st, circuit, gi, K, p, sample_terms):
         gi += 1
     qs, U = circuit.gates[gi]
     c_oracle.build()
+    threads = c_oracle.host_threads()
     t0 = time.perf_counter()
-    k2, a2, info = c_oracle.step(k, a, qs, U, kk, p, True)
-    dt = time.perf_counter() - t0
-    log(f"cpu oracle: {take} terms, K={kk}: {dt:.2f}s")
+    km, am, _ = c_oracle.step(k, a, qs, U, kk, p, True, threads=threads)
+    dt_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    k1, a1, _ = c_oracle.step(k, a, qs, U, kk, p, True)
+    dt_one = time.perf_counter() - t0
+    km, am = c_oracle.sorted_terms(km, am)
+    k1, a1 = c_oracle.sorted_terms(k1, a1)
+    same = bool(np.array_equal(km, k1) and np.array_equal(am.view(np.uint64), a1.view(np.uint64)))
+    model = host_cpu_model()
+    log(f"cpu oracle on {take} terms, K={kk}: {dt_all:.2f}s on {threads} threads, {dt_one:.2f}s on one; "
+        f"same terms: {same}; host {model}, os.cpu_count() = {os.cpu_count()}")
+    if not same:
+        raise SystemExit("the oracle's OpenMP twin differs from the plain oracle")
+    what = (f"the whole steady state ({n} terms), K={kk}" if take == n else
+            f"{take} of the {n} steady-state terms (random subset), K scaled to {kk}")
     return {
-        "value": take / dt,
+        "value": take / dt_all,
         "unit": "updates/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"one gate step (apply + truncate) of the plain C oracle on the whole steady state "
-                   f"({n} terms), K={kk}, p={p}, FP64" if take == n else
-                   f"one gate step (apply + truncate) of the plain C oracle on {take} of the {n} steady-state "
-                   f"terms (random subset), K scaled to {kk}, p={p}, FP64"),
+        "sample": f"one gate step (apply + truncate) of the C oracle, FP64, on {what}, p={p}",
+        "one_core_value": take / dt_one,
+        "cpu_model": model,
+        "host_cpu_count": os.cpu_count(),
     }
+
+
+def bench_copy(args):
+    """The streaming ceiling of this GPU: a device-to-device copy and an
+    elementwise scale of 1 GiB each way, HIP events around each repetition."""
+    import torch
+
+    torch.cuda.init()
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    res = {}
+    for name, fn in (("copy", lambda: dst.copy_(src)), ("scale", lambda: torch.mul(src, 2.0, out=dst))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps if args.steps < 300 else 20):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b) / 1e3)
+        times.sort()
+        med = times[len(times) // 2]
+        res[name] = {"median_s": med, "GBps": 2 * nbytes / med / 1e9, "best_GBps": 2 * nbytes / times[0] / 1e9}
+        log(f"{name}: 2 x {nbytes} bytes, median {med * 1e6:.1f} us, {2 * nbytes / med / 1e9:.0f} GB/s")
+    line = {
+        "metric": "device streaming bandwidth", "value": res["copy"]["GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": len(times), "warmup": 3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": {"workload": "copy_and_scale_1GiB"},
+        "copy": res["copy"], "scale": res["scale"], "peak_GBps": HBM_PEAK_GBS,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -50,13 +50,15 @@
  *     allocated by the library.
  *   - A context is not thread-safe; distinct contexts may run concurrently
  *     on distinct streams.
- *   - STS_E_ARG and STS_E_CAPACITY leave the state as it was, with one
- *     exception: a truncation whose cut exponent holds more candidates than
- *     the side buffer (possible only for untiled 4- and 5-qubit gates on a
- *     state near cap_terms) reports STS_E_CAPACITY from the device and
- *     poisons the context. STS_E_HIP and STS_E_NOMEM during a computation
- *     poison the context too: afterwards only sts_free is valid (other calls
- *     return STS_E_STATE).
+ *   - STS_E_ARG leaves everything as it was. STS_E_CAPACITY is decided on
+ *     the host before any term is written: the gate step that did not fit
+ *     is discarded, and the terms and every figure of sts_stats and
+ *     sts_counters are those from before that gate; the context stays
+ *     usable. STS_E_HIP and STS_E_NOMEM during a computation poison the
+ *     context: afterwards only sts_free is valid (other calls return
+ *     STS_E_STATE). STS_E_STATE also reports a failed internal consistency
+ *     check on the device (a cut that could not be resolved, a write past a
+ *     buffer), which the host's checks rule out; it poisons the context.
  */
 #ifndef STS_H
 #define STS_H
@@ -95,9 +97,11 @@ sts_status sts_required_bytes(uint64_t cap_terms, int precision, size_t *bytes);
  * then top-k (Sec. III). hip_stream: a hipStream_t, NULL = the null stream.
  * arena/arena_bytes: device memory to carve every buffer from (NULL/0 = the
  * library allocates). cap_terms: the most terms the state may ever hold;
- * 0 = max(K, 2^20) when the library allocates, or as many as the arena holds.
- * Gate application needs room for the 2^m * N candidates only when the state
- * is not truncated right after (see sts_apply_gate).
+ * 0 = max(K, 2^20) when the library allocates, or as many as the arena holds
+ * (this argument, the precision, the stream and the arena extend the
+ * two-argument form sts_init(n_qubits, K_or_mass)). Gate application needs
+ * room for the 2^m * N candidates only when the state is not truncated
+ * right after (see sts_apply_gate). STS_E_CAPACITY if K > cap_terms.
  */
 sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass,
                     int precision, void *hip_stream, void *arena, size_t arena_bytes,
@@ -111,14 +115,22 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
  * slower untiled ones (same results). The result is
  * formed lazily: the grouping work runs now, and the new amplitudes are
  * produced by the following sts_truncate (so candidates are never stored),
- * or by the next call that needs them. Returns STS_E_ARG for bad arguments
- * and STS_E_CAPACITY if the un-truncated result of the previous gate does
- * not fit (then that previous gate is dropped and the state is the one
- * before it).
+ * or by the next call that needs them. Returns STS_E_ARG for bad arguments.
+ * Whether a gate's un-truncated result must fit in cap_terms is known only
+ * when the next call arrives (an sts_truncate never forms it), so its
+ * overflow is reported by that next call - this one for the previous gate,
+ * or sts_peak, sts_num_terms, sts_read_terms - as STS_E_CAPACITY: the
+ * previous gate is discarded and the state is the one before it, while the
+ * gate of this call is not applied. Checking at the gate itself would cost a
+ * host synchronisation per gate.
  */
 sts_status sts_apply_gate(sts_ctx *ctx, int m, const int *qubits, const double *U);
 
-/* Truncate by the rule fixed at sts_init (see above) and renormalise. */
+/* Truncate by the rule fixed at sts_init (see above) and renormalise.
+ * STS_E_CAPACITY (the pending gate discarded, nothing else changed) when
+ * the cut keeps more than cap_terms terms (possible only when p-mass alone
+ * limits it), or when an untiled 4- or 5-qubit gate puts more candidates
+ * into the cut's exponent than the side buffer holds (8 x cap_terms). */
 sts_status sts_truncate(sts_ctx *ctx);
 
 /* Most probable key (ties to the smaller key) and its probability
@@ -189,7 +201,13 @@ sts_status sts_kernel_time(sts_ctx *ctx, int kind, int reset, double *total_ms, 
  * (1..5) qubits, listed next in gate_qubits, with the next 2*4^m doubles of
  * gate_U as its matrix (layout of sts_apply_gate); truncate_after[i] != 0
  * truncates right after it. max_terms and mass as in sts_init. The arrays
- * are the caller's and are read during the call. */
+ * are the caller's and are read during the call.
+ * Optional output: when out_keys and out_amps are not NULL, the final terms
+ * are copied there as sts_read_terms does (ascending keys, FP64 (re, im)
+ * pairs; out_keys[out_cap], out_amps[2*out_cap]); the result's n_terms says
+ * how many, and a final state of more than out_cap terms is the circuit's
+ * STS_E_CAPACITY. These arrays must stay valid until the result is
+ * returned (sts_batch_run) or taken (sts_server_wait). */
 typedef struct {
     int n_qubits;
     uint64_t max_terms;
@@ -199,6 +217,9 @@ typedef struct {
     const int *gate_qubits;
     const double *gate_U;
     const uint8_t *truncate_after;
+    uint64_t out_cap;
+    uint64_t *out_keys;
+    double *out_amps;
 } sts_circuit;
 
 typedef struct {

@@ -389,3 +389,287 @@ double orc_fsum_nonneg(uint64_t n, const double *x)
     for (uint64_t i = 0; i < n; ++i) big_add_double(&W, x[i]);
     return big_to_double(&W);
 }
+
+/* ------------------------------------------------------------------------ */
+/* parallel twin (OpenMP)                                                    */
+/*                                                                          */
+/* The same two operations with the work split over host threads, for the  */
+/* sizes where the plain functions above take minutes. Gate application    */
+/* spreads the terms over buckets by a hash of their rest-of-key, so every */
+/* group lies in one bucket, and treats each bucket exactly as orc_apply   */
+/* treats the whole state. Truncation sorts chunks in parallel and merges  */
+/* them into the same total order (weight descending, key ascending; keys  */
+/* are unique, so the order is unique), and splits every exact sum into    */
+/* partial integer sums, which add up to the same integer. The results     */
+/* therefore equal those of orc_apply / orc_truncate bit for bit; only the */
+/* order of the terms after a gate without truncation differs (it is       */
+/* unspecified there). The tests check both against each other.            */
+/* ------------------------------------------------------------------------ */
+#include <omp.h>
+
+static uint32_t mt_bucket(uint64_t rest, uint32_t nb)
+{
+    /* Fibonacci hashing: the top 32 bits of rest * 2^64/phi, reduced */
+    const uint64_t h = rest * 0x9e3779b97f4a7c15ull;
+    return (uint32_t)((h >> 32) % nb);
+}
+
+int orc_apply_mt(uint64_t n, const uint64_t *keys, const double *amps, int m,
+                 const int *qubits, const double *U, uint64_t cap,
+                 uint64_t *n_out, uint64_t *keys_out, double *amps_out, int threads)
+{
+    if (m < 0 || m > 8) return -1;
+    if (threads < 1) threads = 1;
+    uint64_t mask = 0;
+    for (int t = 0; t < m; ++t) {
+        if (qubits[t] < 0 || qubits[t] > 63) return -1;
+        if (mask & (1ull << qubits[t])) return -1;
+        mask |= 1ull << qubits[t];
+    }
+    const int C = threads;                 /* input chunks */
+    const uint32_t NB = 256u * (uint32_t)threads; /* buckets */
+    const uint32_t dim = 1u << m;
+    member *mem = (member *)malloc((n ? n : 1) * sizeof(member));
+    member *srt = (member *)malloc((n ? n : 1) * sizeof(member));
+    uint32_t *bid = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint64_t *cnt = (uint64_t *)calloc((size_t)C * NB, sizeof(uint64_t));
+    uint64_t *bstart = (uint64_t *)malloc(((size_t)NB + 1) * sizeof(uint64_t));
+    uint64_t *bout = (uint64_t *)calloc(NB, sizeof(uint64_t));
+    uint64_t *tk = (uint64_t *)malloc(((n ? n : 1) << m) * sizeof(uint64_t));
+    double *ta = (double *)malloc(((n ? n : 1) << m) * 2 * sizeof(double));
+    int rc = 0;
+    if (!mem || !srt || !bid || !cnt || !bstart || !bout || !tk || !ta) { rc = -1; goto out; }
+
+    /* members, bucket ids and per-chunk bucket counts */
+#pragma omp parallel for num_threads(threads) schedule(static, 1)
+    for (int c = 0; c < C; ++c) {
+        const uint64_t lo = n * (uint64_t)c / C, hi = n * (uint64_t)(c + 1) / C;
+        for (uint64_t i = lo; i < hi; ++i) {
+            uint32_t j = 0;
+            for (int t = 0; t < m; ++t) j |= (uint32_t)((keys[i] >> qubits[t]) & 1) << t;
+            mem[i].rest = keys[i] & ~mask;
+            mem[i].j = j;
+            mem[i].pad = 0;
+            mem[i].idx = i;
+            bid[i] = mt_bucket(mem[i].rest, NB);
+            cnt[(size_t)c * NB + bid[i]] += 1;
+        }
+    }
+    /* bucket-major offsets; within a bucket, chunk order */
+    {
+        uint64_t run = 0;
+        for (uint32_t b = 0; b < NB; ++b) {
+            bstart[b] = run;
+            for (int c = 0; c < C; ++c) {
+                const uint64_t v = cnt[(size_t)c * NB + b];
+                cnt[(size_t)c * NB + b] = run;
+                run += v;
+            }
+        }
+        bstart[NB] = run;
+    }
+#pragma omp parallel for num_threads(threads) schedule(static, 1)
+    for (int c = 0; c < C; ++c) {
+        const uint64_t lo = n * (uint64_t)c / C, hi = n * (uint64_t)(c + 1) / C;
+        for (uint64_t i = lo; i < hi; ++i) srt[cnt[(size_t)c * NB + bid[i]]++] = mem[i];
+    }
+    /* every bucket as orc_apply treats a whole state; its outputs go to a
+     * region of 2^m slots per member */
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 16) reduction(min : rc)
+    for (uint32_t b = 0; b < NB; ++b) {
+        const uint64_t b0 = bstart[b], b1 = bstart[b + 1];
+        member *g = srt + b0;
+        const uint64_t gn = b1 - b0;
+        qsort(g, gn, sizeof(member), cmp_member);
+        uint64_t o = b0 << m;
+        uint64_t g0 = 0;
+        while (g0 < gn) {
+            uint64_t g1 = g0 + 1;
+            while (g1 < gn && g[g1].rest == g[g0].rest) {
+                if (g[g1].j == g[g1 - 1].j) rc = -1; /* duplicate key */
+                ++g1;
+            }
+            for (uint32_t i = 0; i < dim; ++i) {
+                double acc_r = 0.0, acc_i = 0.0;
+                for (uint64_t q = g0; q < g1; ++q) { /* ascending j */
+                    const double vr = amps[2 * g[q].idx], vi = amps[2 * g[q].idx + 1];
+                    const double ur = U[2 * ((uint64_t)i * dim + g[q].j)];
+                    const double ui = U[2 * ((uint64_t)i * dim + g[q].j) + 1];
+                    const double tr = ur * vr - ui * vi;
+                    const double ti = ur * vi + ui * vr;
+                    acc_r = acc_r + tr;
+                    acc_i = acc_i + ti;
+                }
+                if (acc_r != 0.0 || acc_i != 0.0) {
+                    uint64_t dep = 0;
+                    for (int t = 0; t < m; ++t) dep |= (uint64_t)((i >> t) & 1) << qubits[t];
+                    tk[o] = g[g0].rest | dep;
+                    ta[2 * o] = acc_r;
+                    ta[2 * o + 1] = acc_i;
+                    ++o;
+                }
+            }
+            g0 = g1;
+        }
+        bout[b] = o - (b0 << m);
+    }
+    if (rc != 0) goto out;
+    {
+        uint64_t total = 0;
+        for (uint32_t b = 0; b < NB; ++b) {
+            const uint64_t v = bout[b];
+            bout[b] = total;
+            total += v;
+        }
+        if (total > cap) { rc = -2; goto out; }
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 64)
+        for (uint32_t b = 0; b < NB; ++b) {
+            const uint64_t src = bstart[b] << m;
+            const uint64_t len = (b + 1 < NB ? bout[b + 1] : total) - bout[b];
+            memcpy(keys_out + bout[b], tk + src, len * sizeof(uint64_t));
+            memcpy(amps_out + 2 * bout[b], ta + 2 * src, len * 2 * sizeof(double));
+        }
+        *n_out = total;
+    }
+out:
+    free(mem); free(srt); free(bid); free(cnt); free(bstart); free(bout); free(tk); free(ta);
+    if (rc != 0) *n_out = 0;
+    return rc;
+}
+
+/* merge the sorted runs a[s1, s1 + n1) and a[s2, s2 + n2) into d[s1, ...),
+ * keeping only the first `limit` terms of the merged order; returns its length */
+static uint64_t merge_runs(const ritem *a, ritem *d, uint64_t s1, uint64_t n1, uint64_t s2, uint64_t n2,
+                           uint64_t limit)
+{
+    uint64_t i = s1, j = s2, o = s1;
+    const uint64_t e1 = s1 + n1, e2 = s2 + n2, eo = s1 + limit;
+    while (o < eo && i < e1 && j < e2) d[o++] = cmp_rank(&a[j], &a[i]) < 0 ? a[j++] : a[i++];
+    while (o < eo && i < e1) d[o++] = a[i++];
+    while (o < eo && j < e2) d[o++] = a[j++];
+    return o - s1;
+}
+
+int orc_truncate_mt(uint64_t n, uint64_t *keys, double *amps, uint64_t K, double p,
+                    uint64_t *n_out, double *W_out, double *S_out, double *frac_out,
+                    int *dropped_out, int threads)
+{
+    if (threads < 1) threads = 1;
+    const int C = threads;
+    /* with top-k on, only the first K of the ranked list can be kept, and
+     * the first K of a union of sorted runs lie in the first K of each run */
+    const uint64_t need = (K > 0 && K < n) ? K : n;
+    ritem *it = (ritem *)malloc((n ? n : 1) * sizeof(ritem));
+    ritem *buf = (ritem *)malloc((n ? n : 1) * sizeof(ritem));
+    big *part = (big *)malloc((size_t)C * sizeof(big));
+    uint64_t *rs = (uint64_t *)malloc(((size_t)C + 1) * sizeof(uint64_t)); /* run starts */
+    uint64_t *rl = (uint64_t *)malloc(((size_t)C + 1) * sizeof(uint64_t)); /* run lengths */
+    if (!it || !buf || !part || !rs || !rl) { free(it); free(buf); free(part); free(rs); free(rl); return -1; }
+    /* weights, chunk sorts and exact partial totals */
+#pragma omp parallel for num_threads(threads) schedule(static, 1)
+    for (int c = 0; c < C; ++c) {
+        const uint64_t lo = n * (uint64_t)c / C, hi = n * (uint64_t)(c + 1) / C;
+        big_zero(&part[c]);
+        for (uint64_t i = lo; i < hi; ++i) {
+            const double re = amps[2 * i], im = amps[2 * i + 1];
+            it[i].w = re * re + im * im;
+            it[i].key = keys[i];
+            it[i].idx = i;
+            big_add_double(&part[c], it[i].w);
+        }
+        qsort(it + lo, hi - lo, sizeof(ritem), cmp_rank);
+        rs[c] = lo;
+        rl[c] = hi - lo;
+    }
+    big W;
+    big_zero(&W);
+    for (int c = 0; c < C; ++c) big_add(&W, &part[c]);
+    const double Wd = big_to_double(&W);
+    /* pairwise merge rounds; run c absorbs run c + w */
+    for (int w = 1; w < C; w *= 2) {
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
+        for (int c = 0; c < C; c += 2 * w) {
+            const uint64_t n2 = c + w < C ? rl[c + w] : 0;
+            const uint64_t s2 = c + w < C ? rs[c + w] : rs[c];
+            const uint64_t lim = rl[c] + n2 < need ? rl[c] + n2 : need;
+            rl[c] = merge_runs(it, buf, rs[c], rl[c], s2, n2, lim);
+        }
+        ritem *t = it; it = buf; buf = t;
+    }
+    const uint64_t nr = rl[0]; /* the first `need` terms in rank order, from it[0] */
+
+    uint64_t L = n;
+    if (p > 0.0 && p < 1.0) {
+        uint64_t pb;
+        memcpy(&pb, &p, 8);
+        uint64_t pe = (pb >> 52) & 0x7ff, pf = pb & ((1ull << 52) - 1);
+        uint64_t pm = pe ? (pf | (1ull << 52)) : pf;
+        int shift = pe ? (int)(1075 - pe) : 1074;
+        big T, run;
+        big_mul_shr_ceil(&T, &W, pm, shift);
+        /* exact masses of contiguous ranges of the ranked list; the first
+         * range whose inclusive prefix reaches T holds the cut */
+#pragma omp parallel for num_threads(threads) schedule(static, 1)
+        for (int c = 0; c < C; ++c) {
+            big_zero(&part[c]);
+            for (uint64_t i = nr * (uint64_t)c / C; i < nr * (uint64_t)(c + 1) / C; ++i)
+                big_add_double(&part[c], it[i].w);
+        }
+        big_zero(&run);
+        for (int c = 0; c < C; ++c) {
+            big inc = run;
+            big_add(&inc, &part[c]);
+            if (big_cmp(&inc, &T) >= 0) {
+                for (uint64_t i = nr * (uint64_t)c / C; i < nr * (uint64_t)(c + 1) / C; ++i) {
+                    big_add_double(&run, it[i].w);
+                    if (big_cmp(&run, &T) >= 0) { L = i + 1; break; }
+                }
+                break;
+            }
+            run = inc;
+        }
+        /* not reached within the first K terms: L_p > K, and top-k decides */
+    }
+    if (K > 0 && K < L) L = K;
+
+    if (L >= n) {
+        *n_out = n;
+        *W_out = Wd;
+        *S_out = Wd;
+        *frac_out = 1.0;
+        *dropped_out = 0;
+        free(it); free(buf); free(part); free(rs); free(rl);
+        return 0;
+    }
+#pragma omp parallel for num_threads(threads) schedule(static, 1)
+    for (int c = 0; c < C; ++c) {
+        const uint64_t lo = L * (uint64_t)c / C, hi = L * (uint64_t)(c + 1) / C;
+        big_zero(&part[c]);
+        for (uint64_t i = lo; i < hi; ++i) big_add_double(&part[c], it[i].w);
+    }
+    big S;
+    big_zero(&S);
+    for (int c = 0; c < C; ++c) big_add(&S, &part[c]);
+    const double Sd = big_to_double(&S);
+    const double scale = 1.0 / sqrt(Sd);
+
+    uint64_t *nk = (uint64_t *)malloc(L * sizeof(uint64_t));
+    double *na = (double *)malloc(2 * L * sizeof(double));
+    if (!nk || !na) { free(it); free(buf); free(part); free(rs); free(rl); free(nk); free(na); return -1; }
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (uint64_t r = 0; r < L; ++r) {
+        const uint64_t i = it[r].idx;
+        nk[r] = keys[i];
+        na[2 * r] = amps[2 * i] * scale;
+        na[2 * r + 1] = amps[2 * i + 1] * scale;
+    }
+    memcpy(keys, nk, L * sizeof(uint64_t));
+    memcpy(amps, na, 2 * L * sizeof(double));
+    free(nk); free(na); free(it); free(buf); free(part); free(rs); free(rl);
+    *n_out = L;
+    *W_out = Wd;
+    *S_out = Sd;
+    *frac_out = Sd / Wd;
+    *dropped_out = 1;
+    return 0;
+}

@@ -35,7 +35,8 @@ class Circuit(ctypes.Structure):
     """sts_circuit: one circuit of a batch (flattened gate arrays)."""
     _fields_ = [("n_qubits", ctypes.c_int), ("max_terms", ctypes.c_uint64), ("mass", ctypes.c_double),
                 ("n_gates", ctypes.c_uint64), ("gate_m", ctypes.c_void_p), ("gate_qubits", ctypes.c_void_p),
-                ("gate_U", ctypes.c_void_p), ("truncate_after", ctypes.c_void_p)]
+                ("gate_U", ctypes.c_void_p), ("truncate_after", ctypes.c_void_p),
+                ("out_cap", ctypes.c_uint64), ("out_keys", ctypes.c_void_p), ("out_amps", ctypes.c_void_p)]
 
 
 class BatchConfig(ctypes.Structure):

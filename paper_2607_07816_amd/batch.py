@@ -21,28 +21,48 @@ from . import _lib
 
 
 class _Packed:
-    """A circuit flattened into the arrays sts_circuit points at (kept alive here)."""
+    """A circuit flattened into the arrays sts_circuit points at (kept alive
+    here). With want_terms, room for the final terms as well (at most
+    min(K, 2^n) of them, or 2^n without top-k)."""
 
-    def __init__(self, circuit, K: int, p: float):
+    MAX_OUT = 1 << 26
+
+    def __init__(self, circuit, K: int, p: float, want_terms: bool = False):
         self.m = np.ascontiguousarray([len(qs) for qs, _ in circuit.gates], dtype=np.int32)
         self.q = np.ascontiguousarray([q for qs, _ in circuit.gates for q in qs], dtype=np.int32)
         self.u = np.ascontiguousarray(np.concatenate(
             [np.ascontiguousarray(u, dtype=np.complex128).reshape(-1).view(np.float64) for _, u in circuit.gates])
             if circuit.gates else np.zeros(0), dtype=np.float64)
         self.t = np.ascontiguousarray(circuit.truncate_after, dtype=np.uint8)
+        self.keys = self.amps = None
+        cap, kp, ap = 0, None, None
+        if want_terms:
+            full = 1 << min(int(circuit.n), 62)
+            cap = min(int(K), full) if K else full
+            if cap > self.MAX_OUT:
+                raise ValueError(f"final state of up to {cap} terms is too large to return")
+            self.keys = np.zeros(max(cap, 1), dtype=np.uint64)
+            self.amps = np.zeros(max(cap, 1), dtype=np.complex128)
+            kp, ap = self.keys.ctypes.data, self.amps.ctypes.data
         self.c = _lib.Circuit(int(circuit.n), int(K), float(p), len(circuit.gates), self.m.ctypes.data,
-                              self.q.ctypes.data, self.u.ctypes.data, self.t.ctypes.data)
+                              self.q.ctypes.data, self.u.ctypes.data, self.t.ctypes.data, cap, kp, ap)
+
+    def terms(self, n: int):
+        """The final terms (ascending keys) once the circuit has finished."""
+        return self.keys[:n].copy(), self.amps[:n].copy()
 
 
-def pack(items: Sequence[Tuple[object, int, float]]) -> List[_Packed]:
-    return [_Packed(c, K, p) for c, K, p in items]
+def pack(items: Sequence[Tuple[object, int, float]], want_terms: bool = False) -> List[_Packed]:
+    return [_Packed(c, K, p, want_terms) for c, K, p in items]
 
 
-def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, packed=None) -> Tuple[list, float]:
+def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, packed=None,
+              want_terms: bool = False) -> Tuple[list, float]:
     """Run every (circuit, K, p) of `items`; returns (per-circuit result
-    dicts in input order, wall seconds of the whole batch)."""
+    dicts in input order, wall seconds of the whole batch). With want_terms
+    each result also holds the final 'keys' and 'amps' (ascending keys)."""
     L = _lib.load()
-    packed = packed if packed is not None else pack(items)
+    packed = packed if packed is not None else pack(items, want_terms)
     n = len(packed)
     arr = (_lib.Circuit * max(n, 1))(*[pk.c for pk in packed])
     res = (_lib.CircuitResult * max(n, 1))()
@@ -54,9 +74,12 @@ def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, pa
     out = []
     for i in range(n):
         r = res[i]
-        out.append(dict(status=r.status, peak_key=int(r.peak_key), peak_prob=r.peak_prob, n_terms=int(r.n_terms),
-                        gate_steps=int(r.gate_steps), term_updates=int(r.term_updates),
-                        log10_cum_kept=r.log10_cum_kept, seconds=r.seconds))
+        d = dict(status=r.status, peak_key=int(r.peak_key), peak_prob=r.peak_prob, n_terms=int(r.n_terms),
+                 gate_steps=int(r.gate_steps), term_updates=int(r.term_updates),
+                 log10_cum_kept=r.log10_cum_kept, seconds=r.seconds)
+        if packed[i].keys is not None:
+            d["keys"], d["amps"] = packed[i].terms(d["n_terms"])
+        out.append(d)
     return out, dt
 
 

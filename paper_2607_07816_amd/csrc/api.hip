@@ -37,7 +37,7 @@ u64 align_up(u64 x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
-    u64 ctl, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
+    u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
         t_above, t_side, t_off, tctr, dU, sub_cnt, total;
 };
 
@@ -61,6 +61,7 @@ Layout make_layout(u64 cap, int prec)
         return at;
     };
     L.ctl = take(sizeof(DevCtl));
+    L.ctl_save = take(sizeof(DevCtl));
     for (int i = 0; i < 3; ++i) L.keys[i] = take(cap * 8);
     for (int i = 0; i < 3; ++i) L.amps[i] = take(cap * asz);
     L.side_key = take(scap * 8);
@@ -102,6 +103,7 @@ struct sts_ctx {
     GateArg gate;
     u64 n_bound = 1;        // upper bound on the terms in buffer cur
     DevCtl *ctl = nullptr;
+    DevCtl *ctl_save = nullptr; // the control block as it was before a step that may be refused
     u64 *h1 = nullptr, *h2 = nullptr, *best = nullptr;
     u64 *side_key = nullptr, *side_w = nullptr, *sub_key = nullptr, *sub_w = nullptr;
     u32 *rcount = nullptr;                          // per-tile digit counts of a scatter pass
@@ -261,16 +263,31 @@ sts_status sync_ctl(sts_ctx *c)
 {
     STS_TRY(c, hipMemcpyAsync(c->hctl, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, c->stream));
     STS_TRY(c, hipStreamSynchronize(c->stream));
-    const u32 f = c->hctl->flags;
-    if (f & (STS_F_SIDE_OVERFLOW | STS_F_OUT_OVERFLOW)) {
-        c->poisoned = true;
-        return STS_E_CAPACITY;
-    }
-    if (f & STS_F_UNRESOLVED) {
+    // the host's checks keep every write inside its buffer and every cut
+    // resolvable, so a flag here is an internal inconsistency
+    if (c->hctl->flags & (STS_F_SIDE_OVERFLOW | STS_F_OUT_OVERFLOW | STS_F_UNRESOLVED)) {
         c->poisoned = true;
         return STS_E_STATE;
     }
     return STS_OK;
+}
+
+// a gate step that may still be refused for capacity keeps a copy of the
+// control block (term counts, statistics, the previous cut) on the device
+sts_status save_ctl(sts_ctx *c)
+{
+    STS_TRY(c, hipMemcpyAsync(c->ctl_save, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToDevice, c->stream));
+    return STS_OK;
+}
+
+// refuse the pending gate step: the control block goes back to the saved
+// copy, and the state is the sorted input, i.e. the terms before the gate
+sts_status refuse_step(sts_ctx *c)
+{
+    STS_TRY(c, hipMemcpyAsync(c->ctl, c->ctl_save, sizeof(DevCtl), hipMemcpyDeviceToDevice, c->stream));
+    STS_TRY(c, hipStreamSynchronize(c->stream));
+    c->pending = false;
+    return STS_E_CAPACITY;
 }
 
 // group the state in buffer cur by the hash bucket of key & notmask; returns
@@ -437,6 +454,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
         c->own_mem = true;
     }
     c->ctl = (DevCtl *)(c->mem + L.ctl);
+    c->ctl_save = (DevCtl *)(c->mem + L.ctl_save);
     for (int i = 0; i < 3; ++i) {
         c->keys[i] = (u64 *)(c->mem + L.keys[i]);
         c->amps[i] = c->mem + L.amps[i];
@@ -557,10 +575,26 @@ sts_status sts_truncate(sts_ctx *c)
     const int G = hist_groups(c->prec, c->n_bound, c->gate.m, tiled);
     const int tiles = compact_tiles(c->n_bound, c->gate.m);
     const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
+    u64 nb = c->K ? std::min<u64>(c->K, cb) : cb;
+    // two ways a step may not fit, both found before anything is written:
+    // untiled passes (4- and 5-qubit gates on a large state) copy the cut
+    // exponent's candidates to the side buffer in one dense run, which may
+    // exceed it; a cut limited by p-mass alone may keep more than cap terms
+    const bool side_risk = !tiled && cb > c->scap;
+    const bool out_risk = nb > c->cap;
+    if (side_risk || out_risk) {
+        st = save_ctl(c);
+        if (st != STS_OK) return st;
+    }
     b.predict = tiled ? 1 : 0; // the histogram pass also extracts the previous cut exponent
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, tiled, c->stream));
     b.predict = 0;
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, tiled ? 1 : 0, c->stream));
+    if (side_risk) {
+        st = sync_ctl(c);
+        if (st != STS_OK) return st;
+        if (!c->hctl->keep_all && c->hctl->sub_count > c->scap) return refuse_step(c);
+    }
     if (tiled) {
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
     } else {
@@ -574,16 +608,12 @@ sts_status sts_truncate(sts_ctx *c)
     // keeps every slab's loads in flight at once
     STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, tiled ? std::max(sg, tt) : sg, c->stream));
     STS_LAUNCH(c, STS_K_FINAL, launch_final(b, c->stream));
-    u64 nb = c->K ? std::min<u64>(c->K, cb) : cb;
-    if (nb > c->cap) {
+    if (out_risk) {
         // only p-mass limits this cut: learn its size before writing
         st = sync_ctl(c);
         if (st != STS_OK) return st;
         const u64 L = c->hctl->keep_all ? c->hctl->n_cand : c->hctl->L;
-        if (L > c->cap) {
-            c->pending = false;
-            return STS_E_CAPACITY;
-        }
+        if (L > c->cap) return refuse_step(c);
         nb = L;
     }
     if (tiled) {

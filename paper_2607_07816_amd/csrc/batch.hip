@@ -93,7 +93,7 @@ void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, voi
         if (e != hipSuccess) st = STS_E_HIP;
         prev_truncated = true;
     }
-    if (st == STS_OK) st = finish(ctx, r);
+    if (st == STS_OK) st = finish(ctx, c, r);
     if (ctx) sts_free(ctx); // waits for the stream
     graphs.clear();
     r->status = st;

@@ -54,13 +54,17 @@ inline sts_status run_gates(sts_ctx *ctx, const sts_circuit &c, u64 end, u64 *gi
     return st;
 }
 
-// the end-of-circuit figures of a result
-inline sts_status finish(sts_ctx *ctx, sts_circuit_result *r)
+// the end-of-circuit figures of a result, and the final terms if asked for
+inline sts_status finish(sts_ctx *ctx, const sts_circuit &c, sts_circuit_result *r)
 {
     sts_status st = sts_peak(ctx, &r->peak_key, &r->peak_prob); // synchronises
     if (st == STS_OK) st = sts_num_terms(ctx, &r->n_terms);
     if (st == STS_OK) st = sts_counters(ctx, &r->gate_steps, &r->term_updates, nullptr);
     if (st == STS_OK) st = sts_stats(ctx, nullptr, nullptr, &r->log10_cum_kept, nullptr);
+    if (st == STS_OK && c.out_keys && c.out_amps) {
+        uint64_t n = 0;
+        st = sts_read_terms(ctx, c.out_cap, c.out_keys, c.out_amps, &n);
+    }
     return st;
 }
 

@@ -177,7 +177,7 @@ void worker_main(sts_server *s, int w)
                 ++i;
                 continue;
             }
-            if (st == STS_OK) st = finish(r->ctx, &r->res);
+            if (st == STS_OK) st = finish(r->ctx, r->c, &r->res);
             complete(s, r, st);
             active[i] = active.back();
             active.pop_back();

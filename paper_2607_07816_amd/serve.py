@@ -31,17 +31,26 @@ class Server:
         h = ctypes.c_void_p(0)
         _lib._check(L.sts_server_create(ctypes.byref(h), ctypes.byref(cfg)), "sts_server_create")
         self._h = h
+        self._out = {}  # ticket -> packed circuit whose output arrays the server fills
 
-    def submit(self, circuit, K: int = 0, p: float = 0.0) -> int:
-        pk = _Packed(circuit, K, p)  # the server copies the arrays before returning
+    def submit(self, circuit, K: int = 0, p: float = 0.0, want_terms: bool = False) -> int:
+        """Queue a request; with want_terms its result also holds the final
+        'keys' and 'amps' (ascending keys)."""
+        pk = _Packed(circuit, K, p, want_terms)  # the server copies the gate arrays before returning
         t = ctypes.c_uint64(0)
         _lib._check(_lib.load().sts_server_submit(self._h, ctypes.byref(pk.c), ctypes.byref(t)), "sts_server_submit")
+        if want_terms:
+            self._out[int(t.value)] = pk  # its output arrays must outlive the request
         return int(t.value)
 
     def wait(self, ticket: int) -> dict:
         r = _lib.CircuitResult()
         _lib._check(_lib.load().sts_server_wait(self._h, int(ticket), ctypes.byref(r)), "sts_server_wait")
-        return _result(r)
+        out = _result(r)
+        pk = self._out.pop(int(ticket), None)
+        if pk is not None:
+            out["keys"], out["amps"] = pk.terms(out["n_terms"])
+        return out
 
     def stats(self) -> dict:
         v = [ctypes.c_uint64(0) for _ in range(4)]

@@ -55,15 +55,28 @@ def test_batch_equals_alone(prec, streams, graph):
 
 
 def test_batch_fp64_matches_oracle():
+    # every circuit's final terms, term by term, and its figures against the
+    # C oracle run on the same gate list
+    import math
+
+    from oracle import c_oracle as CO
     items = small_items(8, seed=12)
-    res, _ = B.run_batch(items, "c128", 4, 8)
+    res, _ = B.run_batch(items, "c128", 4, 8, want_terms=True)
     for (c, K, p), r in zip(items, res):
-        state = O.run_circuit(c.gates, c.truncate_after, K, p)
-        key, prob = O.peak(state)
-        say(f"[batch] {c.name}: K={K} terms {r['n_terms']} oracle {len(state)} peak {r['peak_key']:#x}")
-        assert r["n_terms"] == len(state)
+        trace = []
+        ko, ao = CO.run_circuit(c.gates, c.truncate_after, K, p, trace=trace)
+        ko, ao = CO.sorted_terms(ko, ao)
+        key, prob = CO.peak(ko, ao)
+        cum = sum(math.log10(t["info"]["fraction"]) for t in trace if t["info"] and t["info"]["dropped"])
+        say(f"[batch] {c.name}: K={K} terms {r['n_terms']} oracle {len(ko)} peak {r['peak_key']:#x}")
+        assert r["status"] == 0
+        assert r["n_terms"] == len(ko)
+        assert np.array_equal(r["keys"], ko)
+        assert np.abs(r["amps"] - ao).max() <= 1e-12
         assert r["peak_key"] == key
         assert abs(r["peak_prob"] - prob) <= 1e-12
+        assert abs(r["log10_cum_kept"] - cum) <= 1e-12
+        assert r["gate_steps"] == sum(1 for t in trace if t["info"] is not None)
 
 
 def test_batch_uneven_sizes_and_order():

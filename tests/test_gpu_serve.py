@@ -1,10 +1,12 @@
 """The serving runtime (sts_server_*): results of requests served together,
 interleaved a few gates at a time and admitted as memory frees, are those of
 the same circuits run alone."""
+import math
 import sys
 import threading
 import time
 
+import numpy as np
 import pytest
 
 from paper_2607_07816_amd import circuits as C
@@ -52,6 +54,30 @@ def test_served_equals_alone(streams, active, turn):
         assert r["latency_seconds"] >= r["seconds"] >= 0 and r["queue_seconds"] >= 0
         for f in FIELDS:
             assert r[f] == ref[f], (c.name, f, r[f], ref[f])
+
+
+def test_served_fp64_matches_oracle():
+    # a served FP64 mix (interleaved a few gates at a time, several streams):
+    # every request's final terms and figures equal the C oracle's on the
+    # same gate list
+    from oracle import c_oracle as CO
+    items = requests(8, seed=24)
+    with Server("c128", 3, 2, 3, hbm_bytes=1 << 30) as srv:
+        tickets = [srv.submit(c, K, p, want_terms=True) for c, K, p in items]
+        res = [srv.wait(t) for t in tickets]
+    for (c, K, p), r in zip(items, res):
+        trace = []
+        ko, ao = CO.run_circuit(c.gates, c.truncate_after, K, p, trace=trace)
+        ko, ao = CO.sorted_terms(ko, ao)
+        key, prob = CO.peak(ko, ao)
+        cum = sum(math.log10(t["info"]["fraction"]) for t in trace if t["info"] and t["info"]["dropped"])
+        say(f"[serve] {c.name}: K={K} p={p} terms {r['n_terms']} oracle {len(ko)} peak {r['peak_key']:#x}")
+        assert r["status"] == 0
+        assert r["n_terms"] == len(ko)
+        assert np.array_equal(r["keys"], ko)
+        assert np.abs(r["amps"] - ao).max() <= 1e-12
+        assert r["peak_key"] == key and abs(r["peak_prob"] - prob) <= 1e-12
+        assert abs(r["log10_cum_kept"] - cum) <= 1e-12
 
 
 def test_admission_waits_for_memory():
