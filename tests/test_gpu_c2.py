@@ -8,12 +8,17 @@ C oracle's OpenMP twin, bitwise equal to the plain one).
 
 FP64: the final key set is identical and the amplitudes agree within 1e-12,
 and every step's kept fraction and total W are equal.
-complex64 (FP32 amplitudes, FP64 masses): the peak bit string is identical,
-every step's kept fraction is within 1e-6 of the oracle's, and the
-cumulative kept mass agrees within 1e-6 relative (|ln M_gpu - ln M_oracle|).
-The per-term error on the common keys, the common fraction of the key sets
-and the mass outside them are printed, not asserted: FP32 keeps other terms
-where two weights straddling the cut differ by less than its rounding.
+
+complex64 (FP32 amplitudes, FP64 masses), every step along the GPU's own
+trajectory: the GPU state before the step (its FP32 amplitudes promoted
+exactly to FP64) goes through one oracle step, and the GPU's step from the
+same state keeps a fraction within 1e-6 of the oracle's, at least 99% of
+the oracle's keys, and per-term errors within 1e-5 on them. At the end the
+peak bit string equals the free-running FP64 oracle's. Free-running, the two
+runs drift apart: where two weights straddling a cut differ by less than
+FP32 rounding, the runs keep different terms, and over some 170 cuts at
+K = 2^20 their key sets and kept fractions separate far beyond 1e-6; that
+drift is printed, not asserted.
 """
 import math
 import sys
@@ -24,7 +29,9 @@ import pytest
 
 from oracle import c_oracle as CO
 from paper_2607_07816_amd import circuits as C
+from paper_2607_07816_amd._lib import State
 from paper_2607_07816_amd.run import run_circuit
+from tests.helpers import check_c64_trajectory
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(400)]
 
@@ -79,23 +86,23 @@ def test_c2_fp64_end_to_end(c2):
     say(f"[c2] peak {key:#x} prob {prob:.6f}, hidden {c.hidden:#x}")
 
 
-def test_c2_c64_end_to_end(c2):
+def test_c2_c64_every_step_and_peak(c2):
     c, cfg, ko, ao, infos = c2
-    say("[c2] GPU c64")
-    kg, ag, key, prob, trace = gpu_run(c, cfg, "c64")
-    assert len(trace) == len(infos)
-    fg = np.array([t["kept_fraction"] for t in trace])
-    fo = np.array([i["fraction"] for i in infos])
-    dmax = float(np.abs(fg - fo).max())
-    dcum = abs(trace[-1]["log10_cum_kept"] - oracle_cum_log10(infos)) * math.log(10.0)
+    K, p = cfg["K"], cfg["p"]
+    say("[c2] GPU c64, each step against the oracle from the GPU's own state")
+    t0 = time.perf_counter()
+    st = State(c.n, K=K, p=p, precision="c64", capacity=K)
+    fg = check_c64_trajectory(st, c, K, p, CO.host_threads(), say)
+    key, prob = st.peak()
+    kg, ag = st.read_terms()
+    st.close()
+    say(f"[c2] c64 checked in {time.perf_counter() - t0:.1f}s")
+    assert len(fg) == len(infos)
     okey, oprob = CO.peak(ko, ao)
-    common, ig, io = np.intersect1d(kg, ko, assume_unique=True, return_indices=True)
-    wo = np.abs(ao) ** 2
-    outside = float(wo.sum() - wo[io].sum())
-    say(f"[c2] c64: max |d kept fraction| {dmax:.2e}, |d ln cumulative| {dcum:.2e}; peak {key:#x} "
-        f"(oracle {okey:#x}), prob {prob:.6f} vs {oprob:.6f}; common keys {len(common) / len(ko):.6f}, "
-        f"oracle mass outside them {outside:.2e}, max per-term error on them "
-        f"{float(np.abs(ag[ig] - ao[io]).max()):.2e}")
     assert key == okey
-    assert dmax <= 1e-6
-    assert dcum <= 1e-6
+    # free-running drift from the FP64 run (reported)
+    fo = np.array([i["fraction"] for i in infos])
+    common = np.intersect1d(kg, ko, assume_unique=True)
+    say(f"[c2] c64 vs free-running FP64: peak {key:#x} (oracle {okey:#x}), prob {prob:.6f} vs {oprob:.6f}; "
+        f"max |d kept fraction| {float(np.abs(np.array(fg) - fo).max()):.2e}; common keys "
+        f"{len(common) / len(ko):.4f}")
