@@ -175,7 +175,8 @@ typedef enum {
     STS_K_SIDE_EXTRACT = 9, /* copy of the mantissa-level subset             */
     STS_K_TILE_KEPT = 10,   /* survivors per tile                            */
     STS_K_TILE_SCAN = 11,   /* output offsets per tile                       */
-    STS_K_COUNT = 12
+    STS_K_SAMPLE = 12,      /* gate on a sample of tiles: the cut's window   */
+    STS_K_COUNT = 13
 } sts_kernel_kind;
 
 /* Turn per-kernel timing on (1) or off (0). While on, every kernel launch is

@@ -28,7 +28,7 @@ EXPORTS = (
 )
 
 KERNEL_KINDS = ("radix_hist", "radix_scan", "radix_pass", "group_hist", "pick1", "group_extract",
-                "side_hist", "final", "group_emit", "side_extract", "tile_kept", "tile_scan")
+                "side_hist", "final", "group_emit", "side_extract", "tile_kept", "tile_scan", "sample")
 
 
 class Circuit(ctypes.Structure):

@@ -38,7 +38,7 @@ u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
     u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
-        t_above, t_side, t_off, tctr, dU, sub_cnt, total;
+        t_above, t_side, t_off, tctr, dU, sub_cnt, wpart, sbins, total;
 };
 
 // tiles of the LDS-tiled passes (2048 terms each) and the side-buffer entries:
@@ -81,6 +81,8 @@ Layout make_layout(u64 cap, int prec)
     L.tctr = take(16 * 4);
     L.dU = take(kULen * 8);
     L.sub_cnt = take((STS_SUB_REGIONS + 1) * 128);
+    L.wpart = take(6 * STS_MAX_GROUPS * 8);
+    L.sbins = take(STS_SW_BANKS * (STS_SW_NB + 4) * 8);
     L.total = o;
     return L;
 }
@@ -113,6 +115,7 @@ struct sts_ctx {
     u32 *tctr = nullptr;
     double *dU = nullptr;
     u32 *sub_cnt = nullptr;
+    u64 *wpart = nullptr, *sbins = nullptr;
     double *hU = nullptr;    // pinned staging of U for m >= 4
     hipEvent_t u_event = nullptr;
     bool u_event_live = false;
@@ -234,6 +237,8 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     b.t_side = c->t_side;
     b.t_off = c->t_off;
     b.tile_ctr = c->tctr + 4;
+    b.wpart = c->wpart;
+    b.sbins = c->sbins;
     return b;
 }
 
@@ -257,6 +262,36 @@ int hist_groups(int prec, u64 n_bound, int m, bool tiled)
 }
 
 int compact_tiles(u64 n_bound, int m) { return (int)sts_compact_groups(n_bound, m); }
+
+// point every buffer of the context into its device memory c->mem
+void bind_layout(sts_ctx *c, const Layout &L)
+{
+    c->ctl = (DevCtl *)(c->mem + L.ctl);
+    c->ctl_save = (DevCtl *)(c->mem + L.ctl_save);
+    for (int i = 0; i < 3; ++i) {
+        c->keys[i] = (u64 *)(c->mem + L.keys[i]);
+        c->amps[i] = c->mem + L.amps[i];
+    }
+    c->side_key = (u64 *)(c->mem + L.side_key);
+    c->side_w = (u64 *)(c->mem + L.side_w);
+    c->sub_key = (u64 *)(c->mem + L.sub_key);
+    c->sub_w = (u64 *)(c->mem + L.sub_w);
+    c->h1 = (u64 *)(c->mem + L.h1);
+    c->h2 = (u64 *)(c->mem + L.h2);
+    c->best = (u64 *)(c->mem + L.best);
+    c->rcount = (u32 *)(c->mem + L.rcount);
+    c->rprefix = (u64 *)(c->mem + L.rprefix);
+    c->rtotal = (u64 *)(c->mem + L.rtotal);
+    c->look_comp = (u64 *)(c->mem + L.look_comp);
+    c->t_above = (u32 *)(c->mem + L.t_above);
+    c->t_side = (u32 *)(c->mem + L.t_side);
+    c->t_off = (u64 *)(c->mem + L.t_off);
+    c->tctr = (u32 *)(c->mem + L.tctr);
+    c->dU = (double *)(c->mem + L.dU);
+    c->sub_cnt = (u32 *)(c->mem + L.sub_cnt);
+    c->wpart = (u64 *)(c->mem + L.wpart);
+    c->sbins = (u64 *)(c->mem + L.sbins);
+}
 
 // copy the control block to the host and wait; map device-side error flags
 sts_status sync_ctl(sts_ctx *c)
@@ -453,29 +488,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
         c->mem = (unsigned char *)p;
         c->own_mem = true;
     }
-    c->ctl = (DevCtl *)(c->mem + L.ctl);
-    c->ctl_save = (DevCtl *)(c->mem + L.ctl_save);
-    for (int i = 0; i < 3; ++i) {
-        c->keys[i] = (u64 *)(c->mem + L.keys[i]);
-        c->amps[i] = c->mem + L.amps[i];
-    }
-    c->side_key = (u64 *)(c->mem + L.side_key);
-    c->side_w = (u64 *)(c->mem + L.side_w);
-    c->sub_key = (u64 *)(c->mem + L.sub_key);
-    c->sub_w = (u64 *)(c->mem + L.sub_w);
-    c->h1 = (u64 *)(c->mem + L.h1);
-    c->h2 = (u64 *)(c->mem + L.h2);
-    c->best = (u64 *)(c->mem + L.best);
-    c->rcount = (u32 *)(c->mem + L.rcount);
-    c->rprefix = (u64 *)(c->mem + L.rprefix);
-    c->rtotal = (u64 *)(c->mem + L.rtotal);
-    c->look_comp = (u64 *)(c->mem + L.look_comp);
-    c->t_above = (u32 *)(c->mem + L.t_above);
-    c->t_side = (u32 *)(c->mem + L.t_side);
-    c->t_off = (u64 *)(c->mem + L.t_off);
-    c->tctr = (u32 *)(c->mem + L.tctr);
-    c->dU = (double *)(c->mem + L.dU);
-    c->sub_cnt = (u32 *)(c->mem + L.sub_cnt);
+    bind_layout(c, L);
 
     hipError_t e = hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->hU, kULen * sizeof(double), hipHostMallocDefault);
@@ -586,7 +599,11 @@ sts_status sts_truncate(sts_ctx *c)
         st = save_ctl(c);
         if (st != STS_OK) return st;
     }
-    b.predict = tiled ? 1 : 0; // the histogram pass also extracts the previous cut exponent
+    // large states: estimate this step's cut on a sample of tiles first, so
+    // that the histogram pass copies a narrow window around it
+    if (tiled && c->gate.m >= 1 && c->gate.m <= 3 && c->n_bound >= STS_SAMPLE_MIN)
+        STS_LAUNCH(c, STS_K_SAMPLE, launch_group_sample(c->prec, c->gate, b, c->stream));
+    b.predict = tiled ? 1 : 0; // the histogram pass also extracts the predicted window
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, tiled, c->stream));
     b.predict = 0;
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, tiled ? 1 : 0, c->stream));
@@ -602,10 +619,13 @@ sts_status sts_truncate(sts_ctx *c)
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT,
                    launch_group_compact(c->prec, STS_KIND_EXTRACT, c->gate, b, tiles, c->stream));
     }
+    // the side passes stream the side buffer; 128 workgroups keep it moving,
+    // and more would only queue more atomics on the shared bins and the
+    // last-workgroup counter
     const int sg = (int)std::min<u64>(std::max<u64>(ceil_div(std::min(cb, c->scap), 256), 1), STS_SIDE_GROUPS);
     STS_LAUNCH(c, STS_K_SIDE_HIST, launch_side_hist(b, c->h2, sg, c->stream));
-    // the extraction has no per-workgroup state: one workgroup per tile slab
-    // keeps every slab's loads in flight at once
+    // the extraction keeps no per-workgroup state: one workgroup per tile
+    // slab keeps every slab's loads in flight at once
     STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, tiled ? std::max(sg, tt) : sg, c->stream));
     STS_LAUNCH(c, STS_K_FINAL, launch_final(b, c->stream));
     if (out_risk) {

@@ -54,7 +54,13 @@ struct DevCtl {
     int dropped;         // L < C: rescale
     int e_star;          // exponent field of the level holding the L-th term
     int e_pred;          // cut exponent of the previous truncation (-1: none)
-    int pred_hit;        // this truncation's cut exponent equals e_pred
+    int pred_hit;        // the histogram pass's side-buffer window holds this truncation's cut
+    // window of weights [w_lo, w_hi] (bit patterns, one exponent field e_w)
+    // that the histogram pass copies to the side buffer: set for this step by
+    // the sampling pass (w_mode = 1), else the octave of e_pred
+    int w_mode;
+    int e_w;
+    u64 w_lo, w_hi;
     int level;           // last resolved level
     u64 cnt_before;      // terms ranked before the current subset
     u64 mb_lo, mb_hi;    // mantissa sum (units 2^(max(e*,1)-1075)) ranked before the subset inside e*

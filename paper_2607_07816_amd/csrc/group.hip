@@ -17,6 +17,8 @@ int group_c128_large_hist_capacity(int m, bool tiled);
 int group_c64_large_hist_capacity(int m, bool tiled);
 hipError_t group_c128_small_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t group_c64_small_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
+hipError_t group_c128_small_sample(const GateArg &g, const PassBufs &b, hipStream_t s);
+hipError_t group_c64_small_sample(const GateArg &g, const PassBufs &b, hipStream_t s);
 hipError_t group_c128_small_emit_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t group_c64_small_emit_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t group_c128_large_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
@@ -55,4 +57,10 @@ hipError_t launch_group_emit_tiles(int prec, const GateArg &g, const PassBufs &b
     if (prec == 0)
         return g.m <= 3 ? group_c128_small_emit_tiles(g, b, tiles, s) : group_c128_large_emit_tiles(g, b, tiles, s);
     return g.m <= 3 ? group_c64_small_emit_tiles(g, b, tiles, s) : group_c64_large_emit_tiles(g, b, tiles, s);
+}
+
+hipError_t launch_group_sample(int prec, const GateArg &g, const PassBufs &b, hipStream_t s)
+{
+    if (g.m < 1 || g.m > 3) return hipErrorInvalidValue; // tiled gates of 1..3 qubits only
+    return prec == 0 ? group_c128_small_sample(g, b, s) : group_c64_small_sample(g, b, s);
 }

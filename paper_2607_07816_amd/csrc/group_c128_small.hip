@@ -48,3 +48,13 @@ hipError_t group_c128_small_emit_tiles(const GateArg &g, const PassBufs &b, int 
     }
     return hipErrorInvalidValue;
 }
+
+hipError_t group_c128_small_sample(const GateArg &g, const PassBufs &b, hipStream_t s)
+{
+    switch (g.m) {
+    case 1: return sample_m<double2, 1>(g, b, s);
+    case 2: return sample_m<double2, 2>(g, b, s);
+    case 3: return sample_m<double2, 3>(g, b, s);
+    }
+    return hipErrorInvalidValue;
+}

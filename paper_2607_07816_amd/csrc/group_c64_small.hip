@@ -48,3 +48,13 @@ hipError_t group_c64_small_emit_tiles(const GateArg &g, const PassBufs &b, int t
     }
     return hipErrorInvalidValue;
 }
+
+hipError_t group_c64_small_sample(const GateArg &g, const PassBufs &b, hipStream_t s)
+{
+    switch (g.m) {
+    case 1: return sample_m<float2, 1>(g, b, s);
+    case 2: return sample_m<float2, 2>(g, b, s);
+    case 3: return sample_m<float2, 3>(g, b, s);
+    }
+    return hipErrorInvalidValue;
+}

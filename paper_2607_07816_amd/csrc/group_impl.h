@@ -596,6 +596,20 @@ __device__ __forceinline__ void flush_bins(const PassBufs &b, u64 *s_hi, u64 *s_
     }
 }
 
+// add a lane's window mantissa sums to the workgroup's (LDS) and clear them
+__device__ __forceinline__ void flush_window(u64 *s_wacc, u64 &ma, u64 &mw)
+{
+    if (ma) {
+        atomicAdd(&s_wacc[1], ma >> 26);
+        atomicAdd(&s_wacc[2], ma & ((1ull << 26) - 1));
+    }
+    if (mw) {
+        atomicAdd(&s_wacc[4], mw >> 26);
+        atomicAdd(&s_wacc[5], mw & ((1ull << 26) - 1));
+    }
+    ma = mw = 0;
+}
+
 // histogram pass over tiles (static tile assignment, persistent grid). With
 // b.predict, the candidates whose exponent field equals the previous step's
 // cut exponent (ctl->e_pred) also go to the tile's side-buffer slab, and the
@@ -608,18 +622,46 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
     __shared__ u64 s_hi[TT_COPIES * TT_NB]; // sum of mantissa >> 26
     __shared__ u64 s_lo[TT_COPIES * TT_NB]; // sum of mantissa & (2^26-1), plus count << 44
     __shared__ u64 s_bw[STS_WG / 64], s_bk[STS_WG / 64];
+    // window sums of the workgroup: candidates above the window, their part in
+    // its exponent (mantissa sum >> 26, & (2^26-1)); candidates inside it, the
+    // same two sums
+    __shared__ u64 s_wacc[6];
     __shared__ u32 s_above, s_side;
     for (int i = threadIdx.x; i < TT_COPIES * TT_NB; i += STS_WG) {
         s_hi[i] = 0;
         s_lo[i] = 0;
     }
+    if (threadIdx.x < 6) s_wacc[threadIdx.x] = 0;
     DevCtl *ctl = b.ctl;
     const u64 n = *b.n_in;
     const u64 *keys = b.keys;
     const AT *amps = (const AT *)b.amps;
     const u64 ntiles = (n + TT_TG - 1) / TT_TG;
-    const int e_pred = b.predict ? ctl->e_pred : -1;
-    const bool predict = e_pred >= 0;
+    // the window of weights [w_lo, w_hi] copied to the side buffer: the one
+    // the sampling pass set for this step, else the previous cut's octave
+    int e_w = -1;
+    u64 w_lo = 0, w_hi = 0;
+    if (b.predict) {
+        if (ctl->w_mode) {
+            e_w = ctl->e_w;
+            w_lo = ctl->w_lo;
+            w_hi = ctl->w_hi;
+        } else if (ctl->e_pred >= 0) {
+            e_w = ctl->e_pred;
+            w_lo = (u64)e_w << 52;
+            w_hi = w_lo | ((1ull << 52) - 1);
+        }
+    }
+    const bool predict = e_w >= 0;
+    // The window's edges are multiples of 2^47 in the weight bits, so the
+    // high words decide: inside when wL <= hi < wH, above when hi >= wH,
+    // above but in the window's exponent when also hi < wE1.
+    const u32 wL = (u32)(w_lo >> 32), wH = (u32)((w_hi + 1) >> 32), wE1 = (u32)(e_w + 1) << 20;
+    // exact mantissa sums of the candidates above the window in its exponent
+    // (ma) and inside it (mw): per lane over at most 8 tiles (< 2^12
+    // mantissas of < 2^53: no overflow), then added to the workgroup's sums
+    // in LDS split at bit 26; their counts come from the per-tile totals
+    u64 ma = 0, mw = 0;
     if (predict && blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->side_dense = 0;
         ctl->side_ntiles = ntiles;
@@ -634,6 +676,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
             // the low sums stay below 2^43 and the counts below 2^17: flush
             __syncthreads();
             flush_bins(b, s_hi, s_lo);
+            if (predict) flush_window(s_wacc, ma, mw);
             since_flush = 0;
         }
         ++since_flush;
@@ -664,12 +707,17 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
                 wbs[i] = wb;
                 const int e_ = (int)(wb >> 52);
                 const u64 key = G.rest | deposit_bits<M>((u32)i, g);
-                if (predict) {
-                    above += (cand && e_ > e_pred) ? 1u : 0u;
-                    sidebits |= (cand && e_ == e_pred) ? (1u << i) : 0u;
-                }
                 if (!cand) continue;
                 const u64 mant = sts_mant(wb);
+                if (predict) {
+                    const u32 hw = (u32)(wb >> 32);
+                    const bool ab = hw >= wH;
+                    const bool inw = hw >= wL && !ab;
+                    above += ab ? 1u : 0u;
+                    sidebits |= inw ? (1u << i) : 0u;
+                    mw += inw ? mant : 0ull;
+                    ma += (ab && hw < wE1) ? mant : 0ull;
+                }
                 const int bin = e_ - TT_EBASE;
                 if (bin >= 0 && bin < TT_NB) {
                     atomicAdd(&s_hi[bin * TT_COPIES + copy], mant >> 26);
@@ -706,6 +754,8 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
             if (threadIdx.x == 0) {
                 b.t_above[tile] = s_above;
                 b.t_side[tile] = s_side;
+                s_wacc[0] += s_above;
+                s_wacc[3] += s_side;
             }
         }
     }
@@ -724,6 +774,13 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
         s_bk[threadIdx.x >> 6] = bk;
     }
     flush_bins(b, s_hi, s_lo);
+    if (predict) {
+        // this workgroup's window sums in its own slots (the pick adds the
+        // workgroups up: no global atomics)
+        flush_window(s_wacc, ma, mw);
+        __syncthreads();
+        if (threadIdx.x < 6) b.wpart[threadIdx.x * STS_MAX_GROUPS + blockIdx.x] = s_wacc[threadIdx.x];
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         u64 w = s_bw[0], k = s_bk[0];
@@ -736,6 +793,182 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
         b.best[blockIdx.x] = w;
         b.best[STS_MAX_GROUPS + blockIdx.x] = k;
     }
+}
+
+// ---------------------------------------------------------------------------
+// sampling pass (large states): the gate on the first STS_SAMPLE_SPAN inputs
+// of STS_SAMPLE_TILES evenly spaced tiles, the candidates' weights counted in
+// fine bins (exponent field and the top STS_SW_FB fraction bits, over the
+// STS_SW_EXPS exponents around the previous cut) with their masses summed in
+// FP32. The last workgroup scales the sample to the whole input, estimates
+// the bin where this step's cut falls (the rule of Sec. III applied to the
+// sample) and sets the window the histogram pass copies to the side buffer:
+// that bin and its two neighbours inside the same exponent field. The
+// estimate only decides which candidates are copied; the cut is still found
+// exactly, and a window that misses it costs the extraction pass. Without a
+// previous cut the pass does nothing (the histogram pass then predicts
+// nothing).
+// ---------------------------------------------------------------------------
+template <typename AT, int M>
+__global__ void __launch_bounds__(STS_WG) k_tile_sample(GateArg g, PassBufs b)
+{
+    constexpr int SPAN = STS_SAMPLE_SPAN; // inputs per workgroup, from a tile's start
+    __shared__ TileSmem<AT> s;
+    __shared__ u32 s_c[STS_SW_NB];
+    __shared__ float s_m[STS_SW_NB];
+    __shared__ u64 s_scan_c[STS_WG / 64];
+    __shared__ double s_scan_m[STS_WG / 64];
+    __shared__ u32 s_flag, s_hit, s_cab;
+    __shared__ float s_mab, s_mbe;
+    static_assert(STS_SW_NB == STS_WG, "one bin per thread in the last workgroup");
+    DevCtl *ctl = b.ctl;
+    const int e_prev = ctl->e_pred;
+    if (e_prev < 0) return; // uniform: nothing to centre the bins on
+    const int e_lo = e_prev - STS_SW_EXPS / 2; // exponent field of bin row 0
+    s_c[threadIdx.x] = 0;
+    s_m[threadIdx.x] = 0.f;
+    if (threadIdx.x == 0) {
+        s_cab = 0;
+        s_mab = 0.f;
+        s_mbe = 0.f;
+    }
+    const u64 n = *b.n_in;
+    const u64 *keys = b.keys;
+    const AT *amps = (const AT *)b.amps;
+    const u64 ntiles = (n + TT_TG - 1) / TT_TG;
+    const u64 stride = ntiles > gridDim.x ? ntiles / gridDim.x : 1;
+    const u64 tile = (u64)blockIdx.x * stride;
+    // STS_SW_BANKS copies of the bins, workgroup w adding to copy w %
+    // STS_SW_BANKS: atomics on one address from every workgroup would queue
+    // behind each other
+    const int bank = (int)(blockIdx.x % STS_SW_BANKS);
+    u32 *gc = reinterpret_cast<u32 *>(b.sbins);                                   // [bank][bin] counts
+    float *gm = reinterpret_cast<float *>(b.sbins + STS_SW_BANKS * STS_SW_NB / 2); // [bank][bin] masses
+    // per bank: [0] inputs sampled, [1] count above the bins, [2] (float) mass
+    // above, [3] (float) mass below
+    u64 *gt = b.sbins + STS_SW_BANKS * STS_SW_NB;
+    __syncthreads();
+    if (tile < ntiles) {
+        const u64 base = tile * TT_TG;
+        const u64 end = base + SPAN < n ? base + SPAN : n;
+        const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
+        const u64 hi = end + TT_H < n ? end + TT_H : n;
+        stage_tile<AT, M>(s, g, keys, amps, lo, hi);
+        __syncthreads();
+        u32 c_above = 0;
+        float m_above = 0.f, m_below = 0.f;
+#pragma unroll 1
+        for (int k = 0; k < SPAN / STS_WG; ++k) {
+            const u64 e = base + (u64)k * STS_WG + threadIdx.x;
+            Group<AT, M> G;
+            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e < end ? e : n, G);
+#pragma unroll Unroll<M>::value
+            for (int i = 0; i < (1 << M); ++i) {
+                const AT o = group_out<AT, M>(g, G, i);
+                if (!G.present || !nonzero(o)) continue;
+                const u64 wb = weight_bits(o);
+                const float w = (float)__longlong_as_double((long long)wb);
+                const int row = (int)(wb >> 52) - e_lo;
+                if (row >= STS_SW_EXPS) {
+                    ++c_above;
+                    m_above += w;
+                } else if (row < 0) {
+                    m_below += w;
+                } else {
+                    const int f = (row << STS_SW_FB) | (int)((wb >> (52 - STS_SW_FB)) & ((1u << STS_SW_FB) - 1));
+                    atomicAdd(&s_c[f], 1u);
+                    atomicAdd(&s_m[f], w);
+                }
+            }
+        }
+        // workgroup totals of the out-of-range parts (wave sums, then LDS),
+        // then one global atomic per non-empty bin and per total, on the
+        // workgroup's bank
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            c_above += __shfl_xor(c_above, d, 64);
+            m_above += __shfl_xor(m_above, d, 64);
+            m_below += __shfl_xor(m_below, d, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&s_cab, c_above);
+            atomicAdd(&s_mab, m_above);
+            atomicAdd(&s_mbe, m_below);
+        }
+        __syncthreads();
+        const u32 cb = s_c[threadIdx.x];
+        if (cb) {
+            atomicAdd(&gc[bank * STS_SW_NB + threadIdx.x], cb);
+            atomicAdd(&gm[bank * STS_SW_NB + threadIdx.x], s_m[threadIdx.x]);
+        }
+        u64 *bt = gt + 4 * bank;
+        if (threadIdx.x == 0) {
+            atomicAdd(&bt[0], end > base ? end - base : 0ull);
+            if (s_cab) {
+                atomicAdd(&bt[1], (u64)s_cab);
+                atomicAdd(reinterpret_cast<float *>(&bt[2]), s_mab);
+            }
+            if (s_mbe != 0.f) atomicAdd(reinterpret_cast<float *>(&bt[3]), s_mbe);
+        }
+    }
+    if (!sts_last_block(&ctl->done[2], &s_flag)) return;
+
+    // the last workgroup: thread t owns bin STS_SW_NB-1-t, so rank order
+    // (weight descending) is thread order
+    const int t = threadIdx.x;
+    const int f = STS_SW_NB - 1 - t;
+    u32 c = 0;
+    double m = 0.0;
+#pragma unroll
+    for (int k = 0; k < STS_SW_BANKS; ++k) {
+        c += ld_agent(&gc[k * STS_SW_NB + f]);
+        m += (double)__int_as_float((int)ld_agent(reinterpret_cast<u32 *>(&gm[k * STS_SW_NB + f])));
+    }
+    u64 sampled = 0, c_above = 0;
+    double m_above = 0.0, m_below = 0.0;
+#pragma unroll
+    for (int k = 0; k < STS_SW_BANKS; ++k) {
+        const u64 *bt = gt + 4 * k;
+        sampled += ld_agent(&bt[0]);
+        c_above += ld_agent(&bt[1]);
+        m_above += (double)__int_as_float((int)ld_agent(reinterpret_cast<const u32 *>(&bt[2])));
+        m_below += (double)__int_as_float((int)ld_agent(reinterpret_cast<const u32 *>(&bt[3])));
+    }
+    u64 ctot;
+    double mtot;
+    const u64 cex = block_excl_scan<u64, STS_WG>((u64)c, s_scan_c, &ctot) + c_above;
+    const double mex = block_excl_scan<double, STS_WG>(m, s_scan_m, &mtot) + m_above;
+    mtot += m_above + m_below;
+    const u64 K = ctl->K;
+    const double p = ctl->p;
+    const bool p_on = p > 0.0 && p < 1.0;
+    // the rule scaled to the sample: K of n terms is K * sampled / n of the
+    // sample; the mass target is p of the sample's own total
+    const double kt = K > 0 && sampled > 0 ? (double)K * (double)sampled / (double)n : 0.0;
+    const double mt = p * mtot;
+    if (t == 0) s_hit = 0xffffffffu;
+    __syncthreads();
+    const bool met_above = (K > 0 && (double)c_above >= kt) || (p_on && m_above >= mt);
+    const bool met = c && ((K > 0 && (double)(cex + c) >= kt) || (p_on && mex + m >= mt));
+    if (sampled > 0 && !met_above && met) atomicMin(&s_hit, (u32)t);
+    __syncthreads();
+    if (t == 0) {
+        const u32 r = s_hit;
+        if (r == 0xffffffffu) {
+            ctl->w_mode = 0;
+        } else {
+            const int fb = STS_SW_NB - 1 - (int)r;
+            const int ex = e_lo + (fb >> STS_SW_FB);
+            const int sub = fb & ((1 << STS_SW_FB) - 1);
+            const int lo_sub = sub > 0 ? sub - 1 : 0;
+            const int hi_sub = sub + 1 < (1 << STS_SW_FB) ? sub + 1 : sub;
+            ctl->e_w = ex;
+            ctl->w_lo = ((u64)ex << 52) | ((u64)lo_sub << (52 - STS_SW_FB));
+            ctl->w_hi = ((u64)ex << 52) + ((u64)(hi_sub + 1) << (52 - STS_SW_FB)) - 1;
+            ctl->w_mode = 1;
+        }
+    }
+    for (int i = t; i < STS_SW_BANKS * (STS_SW_NB + 4); i += STS_WG) st_agent(&b.sbins[i], 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -916,6 +1149,12 @@ hipError_t compact_m(int kind, const GateArg &g, const PassBufs &b, int tiles, h
 template <typename AT, int M> hipError_t extract_tiles_m(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
     hipLaunchKernelGGL((k_tile_extract<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+    return hipGetLastError();
+}
+
+template <typename AT, int M> hipError_t sample_m(const GateArg &g, const PassBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_tile_sample<AT, M>), dim3(STS_SAMPLE_TILES), dim3(STS_WG), 0, s, g, b);
     return hipGetLastError();
 }
 

@@ -53,7 +53,12 @@ struct PassBufs {
     u32 *tile_ctr;
     u32 epoch;            // tags look-back words of this launch
     int materialise;      // 1: keep every candidate, no rescale (no truncation)
-    int predict;          // histogram pass: also extract the predicted cut exponent
+    int predict;          // histogram pass: also extract the window of the predicted cut
+    u64 *wpart;           // [6][STS_MAX_GROUPS]: per histogram workgroup, the count of candidates
+                          // above the window and the mantissa sums (>> 26, & (2^26-1)) of those in
+                          // the window's exponent; then the count and sums of those inside it
+    u64 *sbins;           // sampling pass: STS_SW_BANKS x STS_SW_NB counts (u32), as many masses
+                          // (float), then 4 totals per bank
 };
 
 // launch helpers (return hipError_t of the launch)
@@ -75,6 +80,7 @@ hipError_t launch_side_extract(const PassBufs &b, int grid, hipStream_t s);
 hipError_t launch_tile_kept(const PassBufs &b, int tiles, hipStream_t s);
 hipError_t launch_tile_scan(const PassBufs &b, u64 ntiles_bound, hipStream_t s);
 hipError_t launch_group_extract_tiles(int prec, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
+hipError_t launch_group_sample(int prec, const GateArg &g, const PassBufs &b, hipStream_t s);
 hipError_t launch_group_emit_tiles(int prec, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t launch_final(const PassBufs &b, hipStream_t s);
 hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s);
@@ -95,6 +101,13 @@ inline u64 sts_compact_groups(u64 n, int m)
 #define STS_GROUP_ITEMS 4                       // elements per thread in a compaction tile
 #define STS_GTILE (STS_WG * STS_GROUP_ITEMS)     // elements per compaction tile
 #define STS_MAX_GROUPS 2048                      // workgroups of a histogram pass (best-term slots)
-#define STS_SIDE_GROUPS 512
+#define STS_SIDE_GROUPS 128
 #define STS_SUB_REGIONS 64                        // fill counters of the level-2 subset buffer
 #define STS_SUB_CAP (1u << 16)                   // level-2 subset buffer (terms)
+#define STS_SW_FB 5                              // fraction bits of a sampling bin
+#define STS_SW_EXPS 8                            // exponent fields the sampling bins cover
+#define STS_SW_NB (STS_SW_EXPS << STS_SW_FB)     // sampling bins (256)
+#define STS_SW_BANKS 16                          // copies of the sampling bins in device memory
+#define STS_SAMPLE_TILES 512                     // tiles the sampling pass runs the gate on
+#define STS_SAMPLE_SPAN 512                      // inputs of each, from the tile's start
+#define STS_SAMPLE_MIN (1ull << 22)              // terms from which a step samples first

@@ -26,22 +26,130 @@ __device__ __forceinline__ int unit_bit(int e) { return (e > 0 ? e : 1) - 1; }
 __device__ __forceinline__ u128 make128(u64 lo, u64 hi) { return ((u128)hi << 64) | lo; }
 
 // ---------------------------------------------------------------------------
+// Exact masses, one wave wide: a number of 64 limbs of 64 bits (units
+// 2^-1074), limb i held by lane i. Every lane of the wave takes part in each
+// operation. Carries between limbs are resolved at once from two ballots: a
+// limb generates a carry (its sum wrapped) or propagates one (its sum is all
+// ones), and the carries into the limbs are the carries of the binary sum
+// (G | P) + G, i.e. ((G | P) + G) ^ (G | P) ^ G.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 wl_carry_in(bool gen, bool prop)
+{
+    const u64 G = __ballot(gen), P = __ballot(prop);
+    const u64 X = G | P;
+    return (((X + G) ^ X ^ G) >> sts_lane()) & 1ull;
+}
+
+__device__ __forceinline__ u64 wl_add(u64 a, u64 b)
+{
+    const u64 s = a + b;
+    return s + wl_carry_in(s < a, s == ~0ull);
+}
+
+// a - b, a >= b
+__device__ __forceinline__ u64 wl_sub(u64 a, u64 b)
+{
+    const u64 d = a - b;
+    return d - wl_carry_in(a < b, d == 0);
+}
+
+// this lane's limb of v * 2^bit, v < 2^128 given as (lo, hi)
+__device__ __forceinline__ u64 wl_piece(u64 lo, u64 hi, int bit)
+{
+    const int k = sts_lane() - (bit >> 6), off = bit & 63;
+    if (k == 0) return lo << off;
+    if (k == 1) return off ? (hi << off) | (lo >> (64 - off)) : hi;
+    if (k == 2) return off ? hi >> (64 - off) : 0ull;
+    return 0ull;
+}
+
+// sign of a - b
+__device__ __forceinline__ int wl_cmp(u64 a, u64 b)
+{
+    const u64 D = __ballot(a != b);
+    if (!D) return 0;
+    const int top = 63 - __clzll((long long)D);
+    return ((__ballot(a > b) >> top) & 1ull) ? 1 : -1;
+}
+
+// limb `src` of the number (0 outside 0..63); src may differ between lanes
+__device__ __forceinline__ u64 wl_limb(u64 a, int src)
+{
+    const u64 v = __shfl(a, src & 63, 64);
+    return (src >= 0 && src < 64) ? v : 0ull;
+}
+
+// a >> s (s >= 0), and whether any bit below s was set
+__device__ __forceinline__ u64 wl_shr(u64 a, int s, bool *sticky)
+{
+    const int q = s >> 6, r = s & 63, lane = sts_lane();
+    const u64 a0 = wl_limb(a, lane + q), a1 = wl_limb(a, lane + q + 1);
+    const u64 low = lane < q ? a : (lane == q && r ? (a & ((1ull << r) - 1)) : 0ull);
+    *sticky = __ballot(low != 0) != 0;
+    return r ? (a0 >> r) | (a1 << (64 - r)) : a0;
+}
+
+// ceil(a * m / 2^s), m < 2^64
+__device__ __forceinline__ u64 wl_mul_shr_ceil(u64 a, u64 m, int s)
+{
+    const u128 pr = (u128)a * m;
+    const u64 hi_below = __shfl_up((u64)(pr >> 64), 1, 64);
+    const u64 t = wl_add((u64)pr, sts_lane() > 0 ? hi_below : 0ull);
+    bool sticky;
+    const u64 q = wl_shr(t, s, &sticky);
+    return sticky ? wl_add(q, sts_lane() == 0 ? 1ull : 0ull) : q;
+}
+
+// nearest binary64 (ties to even); the result is the same in every lane
+__device__ inline double wl_to_double(u64 a)
+{
+    const u64 NZ = __ballot(a != 0);
+    if (!NZ) return 0.0;
+    const int top = 63 - __clzll((long long)NZ);
+    const u64 L0 = wl_limb(a, top), L1 = wl_limb(a, top - 1), L2 = wl_limb(a, top - 2);
+    const bool below = top >= 3 && (NZ & ((1ull << (top - 2)) - 1)) != 0;
+    const int lz = __clzll((long long)L0);
+    const int h = top * 64 + 63 - lz; // position of the top set bit
+    if (h < 53) return ldexp((double)L0, -1074);
+    const u64 hi = lz ? (L0 << lz) | (L1 >> (64 - lz)) : L0; // bit 63 = bit h
+    const u64 lo = lz ? (L1 << lz) | (L2 >> (64 - lz)) : L1;
+    const bool rest = below || (lz ? (L2 << lz) != 0 : L2 != 0);
+    u64 mant = hi >> 11;
+    const bool guard = (hi >> 10) & 1ull;
+    const bool sticky = (hi & 0x3ffull) != 0 || lo != 0 || rest;
+    int lsb = h - 52;
+    if (guard && (sticky || (mant & 1ull))) {
+        mant += 1;
+        if (mant == (1ull << 53)) {
+            mant >>= 1;
+            lsb += 1;
+        }
+    }
+    return ldexp((double)mant, lsb - 1074);
+}
+
+// ---------------------------------------------------------------------------
 // level 1: one workgroup of 256 threads. Thread t owns the eight exponent
-// bins 2047-8t .. 2040-8t (descending weight order).
+// bins 2047-8t .. 2040-8t (descending weight order). The bins that hold
+// candidates are listed in rank order in LDS; one wave then adds their exact
+// masses up (the total W and the p-mass target), and walks them again to the
+// first bin where the rule is met.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_only, int predicted)
 {
-    __shared__ Big s_big[256];
-    __shared__ u64 s_cnt[256];
-    __shared__ u64 s_nz[4];
-    __shared__ Big s_tot;
-    __shared__ u64 s_totc;
-    __shared__ Big s_T;
-    __shared__ u32 s_hit;
+    __shared__ u32 s_e[STS_NBIN];   // the non-empty bins in rank order: exponent field,
+    __shared__ u64 s_c[STS_NBIN];   // count,
+    __shared__ u64 s_lo[STS_NBIN];  // mantissa sum (low, high words)
+    __shared__ u64 s_hi[STS_NBIN];
+    __shared__ u32 s_scan[4];
     __shared__ u64 s_bw[4], s_bk[4];
+    __shared__ u64 s_w[6];
     const int t = threadIdx.x;
     DevCtl *ctl = b.ctl;
     u64 *h1 = b.h1;
+    // the exponent of the window the histogram pass copied (predicted steps)
+    const int e_w = predicted ? (ctl->w_mode ? ctl->e_w : ctl->e_pred) : -1;
+    if (t < 6) s_w[t] = 0;
 
     // own bins: every load issued before any is used
     u64 c[8], hi[8], lo[8];
@@ -61,79 +169,41 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         bwv[r] = i < groups ? b.best[i] : 0ull;
         bkv[r] = i < groups ? b.best[STS_MAX_GROUPS + i] : ~0ull;
     }
-    u128 ms[8];
-    Big chunk;
-    big_zero(chunk);
-    u64 ccount = 0;
+    // the window sums of the histogram workgroups: count of candidates above
+    // the window and mantissa sums of those in its exponent, then count and
+    // sums of those inside it
+    if (e_w >= 0) {
+        u64 v[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = t; i < groups; i += 256) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) v[f] += b.wpart[f * STS_MAX_GROUPS + i];
+        }
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) v[f] += __shfl_xor(v[f], d, 64);
+        }
+        __syncthreads(); // s_w cleared
+        if ((t & 63) == 0) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) atomicAdd((unsigned long long *)&s_w[f], (unsigned long long)v[f]);
+        }
+    }
+    // list the non-empty bins in rank order
+    u32 nz = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nz += c[k] ? 1u : 0u;
+    u32 nbins;
+    u32 at = block_excl_scan<u32, 256>(nz, s_scan, &nbins);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        const int e = 2047 - 8 * t - k;
-        ms[k] = ((u128)hi[k] << 26) + (u128)lo[k];
-        ccount += c[k];
-        if (c[k]) big_add_shifted(chunk, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
-    }
-    // prefixes in rank order. Only the few threads whose bins hold candidates
-    // matter (the others' prefixes equal their predecessor's), so one thread
-    // walks those in order: s_big / s_cnt become their exclusive prefixes, and
-    // s_tot / s_totc the totals.
-    s_big[t] = chunk;
-    s_cnt[t] = ccount;
-    const u64 nzmask = __ballot(ccount != 0);
-    if ((t & 63) == 0) s_nz[t >> 6] = nzmask;
-    __syncthreads();
-    if (t == 0) {
-        Big acc;
-        big_zero(acc);
-        u64 cacc = 0;
-        for (int w = 0; w < 4; ++w) {
-            u64 m = s_nz[w];
-            while (m) {
-                const int i = 64 * w + __ffsll((long long)m) - 1;
-                m &= m - 1;
-                const Big own = s_big[i];
-                const u64 oc = s_cnt[i];
-                s_big[i] = acc;
-                s_cnt[i] = cacc;
-                big_add(acc, own);
-                cacc += oc;
-            }
-        }
-        s_tot = acc;
-        s_totc = cacc;
-    }
-    __syncthreads();
-    const bool nz = ccount != 0;
-    Big excl = s_big[t];       // meaningful where nz
-    const u64 cexcl = s_cnt[t];
-    big_add(chunk, excl);      // inclusive
-    ccount += cexcl;
-    // chunk / ccount now inclusive where nz
-    const u64 total_c = s_totc;
-    if (t == 0) {
-        Big W = s_tot;
-        const double Wd = big_to_double(W);
-        ctl->cand_all = total_c;
-        if (peak_only) {
-            ctl->peak_W = Wd;
-        } else {
-            ctl->W = Wd;
-            ctl->n_cand = total_c;
-            ctl->tot_steps += 1;
-            ctl->tot_updates += *b.n_in;
-            ctl->tot_cand += total_c;
-            const double p = ctl->p;
-            if (p > 0.0 && p < 1.0) {
-                const u64 pb = sts_dbits(p);
-                const u64 pe = pb >> 52, pf = pb & ((1ull << 52) - 1);
-                const u64 pm = pe ? (pf | (1ull << 52)) : pf;
-                const int sh = pe ? (int)(1075 - pe) : 1074;
-                Big T;
-                big_mul_shr_ceil(T, W, pm, sh);
-                s_T = T;
-                ctl->T = T;
-            }
-        }
-        s_hit = 0xffffffffu;
+        if (!c[k]) continue;
+        s_e[at] = (u32)(2047 - 8 * t - k);
+        s_c[at] = c[k];
+        const u128 ms = ((u128)hi[k] << 26) + (u128)lo[k];
+        s_lo[at] = (u64)ms;
+        s_hi[at] = (u64)(ms >> 64);
+        ++at;
     }
     // peak: reduce the per-workgroup bests (written by the identity pass of
     // sts_peak only)
@@ -162,97 +232,128 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         }
     }
     __syncthreads();
-    if (peak_only && t == 0) {
-        u64 w = s_bw[0], k = s_bk[0];
-        for (int i = 1; i < 4; ++i)
-            if (s_bw[i] > w || (s_bw[i] == w && s_bk[i] < k)) {
-                w = s_bw[i];
-                k = s_bk[i];
-            }
-        ctl->peak_key = k;
-        ctl->peak_w = (w >> 63) ? __longlong_as_double((long long)(w & ~(1ull << 63))) : 0.0;
-    }
-    if (peak_only) {
-        __syncthreads();
-        for (int i = t; i < 3 * STS_NBIN; i += 256) h1[i] = 0;
-        return;
-    }
 
-    // first bin (in rank order) where the rule is met. Prefixes only grow in
-    // rank order, so it lies in the first thread whose inclusive prefix meets
-    // the rule; that thread alone walks its bins.
-    const u64 K = ctl->K;
-    const double p = ctl->p;
-    const bool p_on = p > 0.0 && p < 1.0;
-    const bool t_hit = nz && ((K > 0 && ccount >= K) || (p_on && big_cmp(chunk, s_T) >= 0));
-    if (t_hit) atomicMin(&s_hit, (u32)t);
-    __syncthreads();
-    u32 hit = 0xffffffffu;
-    Big S_hit;
-    u64 cnt_hit = 0;
-    if ((u32)t == s_hit) {
-        Big S = excl;
-        u64 cnt = cexcl;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (hit == 0xffffffffu && c[k]) {
-                const int e = 2047 - 8 * t - k;
-                Big inc = S;
-                big_add_shifted(inc, (u64)ms[k], (u64)(ms[k] >> 64), unit_bit(e));
-                const bool hk = K > 0 && cnt + c[k] >= K;
-                const bool hp = p_on && big_cmp(inc, s_T) >= 0;
+    if (t < 64) { // one wave: exact sums over the listed bins
+        const int lane = t;
+        u64 W = 0, total_c = 0;
+        for (u32 j = 0; j < nbins; ++j) {
+            W = wl_add(W, wl_piece(s_lo[j], s_hi[j], unit_bit((int)s_e[j])));
+            total_c += s_c[j];
+        }
+        const double Wd = wl_to_double(W);
+        if (peak_only) {
+            if (lane == 0) {
+                ctl->cand_all = total_c;
+                ctl->peak_W = Wd;
+                u64 w = s_bw[0], k = s_bk[0];
+                for (int i = 1; i < 4; ++i)
+                    if (s_bw[i] > w || (s_bw[i] == w && s_bk[i] < k)) {
+                        w = s_bw[i];
+                        k = s_bk[i];
+                    }
+                ctl->peak_key = k;
+                ctl->peak_w = (w >> 63) ? __longlong_as_double((long long)(w & ~(1ull << 63))) : 0.0;
+            }
+        } else {
+            const u64 K = ctl->K;
+            const double p = ctl->p;
+            const bool p_on = p > 0.0 && p < 1.0;
+            // p-mass target T = ceil(p * W), exactly
+            u64 T = 0;
+            if (p_on) {
+                const u64 pb = sts_dbits(p);
+                const u64 pe = pb >> 52, pf = pb & ((1ull << 52) - 1);
+                const u64 pm = pe ? (pf | (1ull << 52)) : pf;
+                const int sh = pe ? (int)(1075 - pe) : 1074;
+                T = wl_mul_shr_ceil(W, pm, sh);
+            }
+            if (lane < STS_NL) ctl->T.l[lane] = T;
+            if (lane == 0) {
+                ctl->cand_all = total_c;
+                ctl->W = Wd;
+                ctl->n_cand = total_c;
+                ctl->tot_steps += 1;
+                ctl->tot_updates += *b.n_in;
+                ctl->tot_cand += total_c;
+            }
+            // the first bin in rank order where the rule is met
+            u64 S = 0, cnt = 0;
+            u32 hit = 0xffffffffu;
+            for (u32 j = 0; j < nbins; ++j) {
+                const u64 inc = wl_add(S, wl_piece(s_lo[j], s_hi[j], unit_bit((int)s_e[j])));
+                const bool hk = K > 0 && cnt + s_c[j] >= K;
+                const bool hp = p_on && wl_cmp(inc, T) >= 0;
                 if (hk || hp) {
-                    hit = (u32)(8 * t + k);
-                    S_hit = S;
-                    cnt_hit = cnt;
-                } else {
-                    S = inc;
-                    cnt += c[k];
+                    hit = j;
+                    break;
+                }
+                S = inc;
+                cnt += s_c[j];
+            }
+            if (hit == 0xffffffffu) {
+                if (lane == 0) {
+                    ctl->keep_all = 1;
+                    ctl->dropped = 0;
+                    ctl->L = total_c;
+                    ctl->scale = 1.0;
+                    ctl->S = Wd;
+                    ctl->frac = 1.0;
+                    ctl->level = 1;
+                    ctl->pred_hit = 0;
+                    ctl->e_pred = -1;
+                }
+            } else {
+                const int e = (int)s_e[hit];
+                const int ub = unit_bit(e);
+                // does the copied window hold the cut? Exactly when the rule is
+                // not met through the candidates above it and is met through it
+                bool in_window = false;
+                u64 ca = 0, cw = 0;
+                u128 ma = 0;
+                if (e == e_w) {
+                    // the histogram pass counted every candidate above the window;
+                    // those in exponents above e are the cnt ranked before this bin
+                    ca = s_w[0] - cnt;
+                    cw = s_w[3];
+                    ma = ((u128)s_w[1] << 26) + (u128)s_w[2];
+                    const u128 mw = ((u128)s_w[4] << 26) + (u128)s_w[5];
+                    const u64 Sa = wl_add(S, wl_piece((u64)ma, (u64)(ma >> 64), ub));
+                    const bool met_a = (K > 0 && cnt + ca >= K) || (p_on && wl_cmp(Sa, T) >= 0);
+                    const u64 Sw = wl_add(Sa, wl_piece((u64)mw, (u64)(mw >> 64), ub));
+                    const bool met_w = (K > 0 && cnt + ca + cw >= K) || (p_on && wl_cmp(Sw, T) >= 0);
+                    in_window = !met_a && met_w;
+                }
+                // remaining mass to reach inside the bin, in its units (rounded up)
+                u64 R_lo = ~0ull, R_hi = ~0ull;
+                if (p_on) {
+                    bool sticky;
+                    const u64 q = wl_shr(wl_sub(T, S), ub, &sticky);
+                    const bool over = __ballot(lane >= 2 && q != 0) != 0;
+                    u128 r = ((u128)__shfl(q, 1, 64) << 64) | (u128)__shfl(q, 0, 64);
+                    if (!over) {
+                        if (sticky) r += 1;
+                        if (r != 0 || !sticky) {
+                            R_lo = (u64)r;
+                            R_hi = (u64)(r >> 64);
+                        }
+                    }
+                }
+                if (lane < STS_NL) ctl->S_excl.l[lane] = S;
+                if (lane == 0) {
+                    ctl->keep_all = 0;
+                    ctl->pred_hit = in_window ? 1 : 0;
+                    ctl->e_pred = e;
+                    ctl->e_star = e;
+                    ctl->cnt_before = in_window ? cnt + ca : cnt;
+                    ctl->sub_count = in_window ? cw : s_c[hit];
+                    ctl->mb_lo = in_window ? (u64)ma : 0;
+                    ctl->mb_hi = in_window ? (u64)(ma >> 64) : 0;
+                    ctl->level = 1;
+                    ctl->R_lo = R_lo;
+                    ctl->R_hi = R_hi;
                 }
             }
-        }
-    }
-    __syncthreads();
-    if (t == 0) s_hit = 0xffffffffu;
-    __syncthreads();
-    if (hit != 0xffffffffu) atomicMin(&s_hit, hit);
-    __syncthreads();
-    const u32 first = s_hit;
-    if (first == 0xffffffffu) {
-        if (t == 0) {
-            ctl->keep_all = 1;
-            ctl->dropped = 0;
-            ctl->L = total_c;
-            ctl->scale = 1.0;
-            ctl->S = ctl->W;
-            ctl->frac = 1.0;
-            ctl->level = 1;
-            ctl->pred_hit = 0;
-            ctl->e_pred = -1;
-        }
-    } else if (hit == first) {
-        const int e = 2047 - (int)first;
-        const int k = (int)first - 8 * t;
-        ctl->keep_all = 0;
-        ctl->pred_hit = (predicted && ctl->e_pred == e) ? 1 : 0;
-        ctl->e_pred = e;
-        ctl->e_star = e;
-        ctl->cnt_before = cnt_hit;
-        ctl->S_excl = S_hit;
-        ctl->sub_count = c[k];
-        ctl->mb_lo = 0;
-        ctl->mb_hi = 0;
-        ctl->level = 1;
-        if (p_on) {
-            Big D = s_T;
-            big_sub(D, S_hit);
-            u64 lo, hi;
-            big_shr_ceil_u128(D, unit_bit(e), lo, hi);
-            ctl->R_lo = lo;
-            ctl->R_hi = hi;
-        } else {
-            ctl->R_lo = ~0ull;
-            ctl->R_hi = ~0ull;
+            if (lane == 0) ctl->w_mode = 0; // a window serves one step
         }
     }
     __syncthreads();
@@ -542,7 +643,7 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
     if (!sts_last_block(&ctl->done[1], &s_flag)) return;
     if (threadIdx.x == 0) {
         s_sub.cnt_before = ctl->cnt_before;
-        s_sub.mb = 0;
+        s_sub.mb = make128(ctl->mb_lo, ctl->mb_hi); // the window's exponent above it, or 0
         s_sub.vpre = 0;
         s_sub.vshift = 116;
         s_sub.count = ctl->sub_count;
@@ -958,3 +1059,4 @@ hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s)
     hipLaunchKernelGGL(k_set_n, dim3(1), dim3(1), 0, s, n_out, n);
     return hipGetLastError();
 }
+

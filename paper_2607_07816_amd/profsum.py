@@ -30,7 +30,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 SHORT_NAMES = ("k_radix_pass", "k_radix_count", "k_radix_hist", "k_radix_scan", "k_tile_hist", "k_tile_extract", "k_tile_emit",
                "k_tile_compact", "k_group_hist", "k_group_compact", "k_group_extract", "k_group_emit", "k_pick1",
                "k_side_hist", "k_side_extract", "k_final", "k_tile_kept", "k_tile_scan", "k_init_state",
-               "k_set_n")
+               "k_set_n", "k_tile_sample", "k_fill_zero", "k_ctl_begin", "k_terms_out")
 
 
 def short(name: str) -> str:

@@ -1,0 +1,116 @@
+"""Gate steps on states large enough for the sampling pass (needs the GPU).
+
+From 2^22 input terms a step first runs the gate on a sample of tiles to
+estimate where the cut falls (Sec. III rule applied to the sample), and the
+histogram pass copies only a narrow window of weights around the estimate to
+the side buffer. The window only steers the work: when it holds the cut the
+extraction pass is skipped, when it misses, the extraction pass copies the
+cut's whole exponent octave. Either way the cut is exact, so these steps are
+compared with the oracle bit for bit (FP64) or within the per-step
+tolerances (complex64):
+  * a smooth random state cut by top-k (the estimate holds the cut),
+  * the same cut by p-mass,
+  * a state whose mass sits mostly in a few heavy terms that the sample
+    cannot see, cut by p-mass (the estimate misses),
+  * a cut whose threshold weight is shared by many terms (ties broken by
+    key inside the window).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import c_oracle as CO
+from paper_2607_07816_amd import circuits as C
+from tests.helpers import random_state
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(300)]
+
+N_BIG = (1 << 22) + 4321
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def one_step(keys, amps, n, qs, U, K, p, prec):
+    from paper_2607_07816_amd import _lib
+    # a p-mass cut alone may keep up to every candidate (2^m per input)
+    cap = max(len(keys), K, 1 << 20) if K else len(keys) << len(qs)
+    with _lib.State(n, K=K, p=p, precision=prec, capacity=cap) as st:
+        st.load_terms(keys, amps)
+        st.apply_gate(qs, U)
+        st.truncate()
+        kg, ag = st.read_terms()
+        stats = st.stats()
+    ko, ao, info = CO.step(keys, amps, qs, U, K, p, True, CO.host_threads())
+    ko, ao = CO.sorted_terms(ko, ao)
+    return kg, ag, stats, ko, ao, info
+
+
+def check(kg, ag, stats, ko, ao, info, prec):
+    say(f"  gpu {len(kg)} terms, oracle {len(ko)}; kept fraction {stats['kept_fraction']:.12f} "
+        f"vs {info['fraction']:.12f}")
+    if prec == "c128":
+        assert np.array_equal(kg, ko)
+        assert np.array_equal(ag.view(np.uint64), ao.view(np.uint64))
+        assert stats["kept_fraction"] == info["fraction"]
+        assert stats["W"] == info["W"]
+    else:
+        assert abs(stats["kept_fraction"] - info["fraction"]) <= 1e-6
+        common, ig, io = np.intersect1d(kg, ko, assume_unique=True, return_indices=True)
+        assert len(common) >= 0.99 * len(ko)
+        assert np.abs(ag[ig] - ao[io]).max() <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def smooth():
+    rng = np.random.default_rng(2207)
+    keys, amps = random_state(rng, 40, N_BIG)
+    return keys, amps
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("K,p", [(N_BIG, 0.0), (0, 0.9), (3 << 21, 0.97)])
+def test_sampled_window_step(smooth, prec, K, p):
+    keys, amps = smooth
+    if prec == "c64":
+        amps = amps.astype(np.complex64).astype(np.complex128)
+    rng = np.random.default_rng(K + int(p * 1000))
+    qs = tuple(int(q) for q in rng.choice(40, size=2, replace=False))
+    U = C.haar_su(rng, 4)
+    say(f"window step {prec} N={len(keys)} K={K} p={p} gate {qs}")
+    check(*one_step(keys, amps, 40, qs, U, K, p, prec), prec)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_window_missed_by_heavy_terms(prec):
+    # 16 terms hold about 60% of the mass: the sample sees none of them, so
+    # its p-mass estimate falls far below the true cut
+    rng = np.random.default_rng(909)
+    keys, amps = random_state(rng, 44, N_BIG, normalise=False)
+    heavy = rng.choice(len(keys), size=16, replace=False)
+    amps[heavy] *= np.sqrt(0.6 / 0.4 * len(keys) / 16)
+    amps /= np.linalg.norm(amps)
+    if prec == "c64":
+        amps = amps.astype(np.complex64).astype(np.complex128)
+    qs = (3, 41)
+    U = C.haar_su(rng, 4)
+    say(f"heavy-term step {prec}")
+    check(*one_step(keys, amps, 44, qs, U, 0, 0.8, prec), prec)
+
+
+def test_window_ties_at_the_cut():
+    # every amplitude has modulus 2^-11 or 2^-12 and the gate is a product of
+    # Hadamards: the weights take few values, so the cut's weight is shared by
+    # a great many candidates and the key decides among them
+    rng = np.random.default_rng(31)
+    keys, _ = random_state(rng, 36, N_BIG)
+    mag = np.where(rng.random(len(keys)) < 0.5, 2.0 ** -11, 2.0 ** -12)
+    amps = mag * np.exp(1j * (np.pi / 2) * rng.integers(0, 4, len(keys)))
+    h = np.array([[1, 1], [1, -1]]) / np.sqrt(2.0)
+    U = np.kron(h, h).astype(np.complex128)
+    K = len(keys) + 77777
+    say("tie step c128")
+    check(*one_step(keys, amps, 36, (0, 20), U, K, 0.0, "c128"), "c128")
