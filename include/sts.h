@@ -303,6 +303,38 @@ sts_status sts_server_stats(sts_server *s, uint64_t *queued, uint64_t *active, u
  * Results not taken are dropped. NULL is a no-op. */
 void sts_server_destroy(sts_server *s);
 
+/* ------------------------------------------------------------------------
+ * One gate step with no allocation of any kind, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.
+ *
+ * Applies U (host array, layout of sts_apply_gate) on qubits[0..m-1]
+ * (1 <= m <= 3) to the n_in terms in keys_in / amps_in, truncates by the
+ * rule (max_terms = K >= 1, required; mass = p as in sts_init) and
+ * renormalises - the results of sts_load_terms, sts_apply_gate and
+ * sts_truncate on a context - and writes the kept terms to keys_out /
+ * amps_out and their count to *n_out. All five arrays are the caller's
+ * device memory: keys u64, amplitudes double2 (STS_C128) or float2
+ * (STS_C64); the outputs need room for min(K, 2^n_qubits) terms and must
+ * not overlap the inputs; n_out points to one u64 in device memory; stats,
+ * if not NULL, to two doubles in device memory that receive W and the kept
+ * fraction (as sts_stats). Terms come out in no particular order.
+ * Every working buffer lives in one static device array of 16 MiB per
+ * device (held until the process ends), laid out for at most
+ * STS_STATIC_MAX_TERMS terms: n_in or K above that is STS_E_CAPACITY, with
+ * nothing launched. The call only enqueues work on hip_stream (NULL = the
+ * null stream) and returns without waiting; it launches kernels and
+ * device-to-device copies only. Each call overwrites the array, so calls
+ * that overlap in time on one device (other streams, other threads) race:
+ * order them on one stream or serialise them. STS_E_ARG for bad arguments
+ * (nothing launched); STS_E_HIP if a launch fails.
+ * ------------------------------------------------------------------------ */
+#define STS_STATIC_MAX_TERMS 65536
+sts_status sts_step_static(int n_qubits, uint64_t max_terms, double mass, int precision, void *hip_stream,
+                           int m, const int *qubits, const double *U,
+                           const uint64_t *keys_in, const void *amps_in, uint64_t n_in,
+                           uint64_t *keys_out, void *amps_out, uint64_t *n_out, double *stats);
+
 /* Release the context and the device memory it allocated. NULL is a no-op. */
 void sts_free(sts_ctx *ctx);
 

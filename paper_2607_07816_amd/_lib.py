@@ -25,7 +25,9 @@ EXPORTS = (
     "sts_num_terms", "sts_read_terms", "sts_load_terms", "sts_stats", "sts_counters",
     "sts_profile", "sts_kernel_time", "sts_free", "sts_strerror", "sts_batch_run",
     "sts_server_create", "sts_server_submit", "sts_server_wait", "sts_server_stats", "sts_server_destroy",
+    "sts_step_static",
 )
+STATIC_MAX_TERMS = 65536  # STS_STATIC_MAX_TERMS
 
 KERNEL_KINDS = ("radix_hist", "radix_scan", "radix_pass", "group_hist", "pick1", "group_extract",
                 "side_hist", "final", "group_emit", "side_extract", "tile_kept", "tile_scan", "sample")
@@ -106,6 +108,7 @@ def load() -> ctypes.CDLL:
     L.sts_server_stats.argtypes = [vp] + [ctypes.POINTER(u64)] * 4
     L.sts_server_destroy.argtypes = [vp]
     L.sts_server_destroy.restype = None
+    L.sts_step_static.argtypes = [i32, u64, dbl, i32, vp, i32, vp, vp, vp, vp, u64, vp, vp, vp, vp]
     L.sts_strerror.argtypes = [i32]
     L.sts_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -124,6 +127,21 @@ def _check(rc: int, what: str):
         raise CapacityError(rc, what)
     if rc != STS_OK:
         raise StsError(rc, what)
+
+
+def step_static(n_qubits: int, K: int, p: float, precision, qubits: Sequence[int], U: np.ndarray,
+                keys_in: int, amps_in: int, n_in: int, keys_out: int, amps_out: int, n_out: int,
+                stats: int = 0, stream: int = 0) -> None:
+    """sts_step_static: one gate step on device arrays given by address
+    (keys u64, amplitudes complex128/complex64; n_out one u64, stats two
+    doubles or 0), with no allocation; only enqueues work on the stream."""
+    qs = (ctypes.c_int * len(qubits))(*[int(q) for q in qubits])
+    u = np.ascontiguousarray(U, dtype=np.complex128)
+    vp = ctypes.c_void_p
+    _check(load().sts_step_static(int(n_qubits), int(K), float(p), _prec(precision), vp(stream or None), len(qubits),
+                                  qs, u.ctypes.data_as(vp), vp(keys_in or None), vp(amps_in or None), int(n_in),
+                                  vp(keys_out or None), vp(amps_out or None), vp(n_out or None), vp(stats or None)),
+           "sts_step_static")
 
 
 def required_bytes(cap_terms: int, precision: int) -> int:

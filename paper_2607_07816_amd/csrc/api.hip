@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -85,6 +86,33 @@ Layout make_layout(u64 cap, int prec)
     L.sbins = take(STS_SW_BANKS * (STS_SW_NB + 4) * 8);
     L.total = o;
     return L;
+}
+
+// the working memory of sts_step_static: one array per device, holding a
+// context laid out for STS_STATIC_MAX_TERMS terms of either precision
+constexpr size_t kStaticBytes = 16ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// its address on the current device (the array's name is a host-side
+// stand-in, never a device address); looked up once per device
+hipError_t static_scratch(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 } // namespace
@@ -798,6 +826,56 @@ sts_status sts_kernel_time(sts_ctx *c, int kind, int reset, double *total_ms, ui
             c->prof_n[k] = 0;
         }
     }
+    return STS_OK;
+}
+
+sts_status sts_step_static(int n_qubits, uint64_t max_terms, double mass, int precision, void *hip_stream, int m,
+                           const int *qubits, const double *U, const uint64_t *keys_in, const void *amps_in,
+                           uint64_t n_in, uint64_t *keys_out, void *amps_out, uint64_t *n_out, double *stats)
+{
+    if (n_qubits < 1 || n_qubits > 64 || (precision != STS_C128 && precision != STS_C64)) return STS_E_ARG;
+    if (!(mass == mass) || !qubits || !U || m < 1 || m > 3 || m > n_qubits) return STS_E_ARG;
+    if ((n_in && (!keys_in || !amps_in)) || !keys_out || !amps_out || !n_out) return STS_E_ARG;
+    if (n_qubits < 64) max_terms = std::min<u64>(max_terms, 1ull << n_qubits);
+    if (max_terms == 0) return STS_E_ARG; // top-k bounds the result and the caller's output arrays
+    if (max_terms > STS_STATIC_MAX_TERMS || n_in > STS_STATIC_MAX_TERMS) return STS_E_CAPACITY;
+    const Layout L = make_layout(STS_STATIC_MAX_TERMS, precision);
+    if (L.total > kStaticBytes) return STS_E_CAPACITY;
+    void *base = nullptr;
+    if (static_scratch(&base) != hipSuccess) return STS_E_HIP;
+
+    // a context on the stack over the static array: with gates of at most 3
+    // qubits and top-k within the capacity, the gate step never synchronises,
+    // never allocates and is never refused
+    sts_ctx c;
+    c.n_qubits = n_qubits;
+    c.prec = precision;
+    c.K = max_terms;
+    c.p = (mass > 0.0 && mass < 1.0) ? mass : 0.0;
+    c.stream = (hipStream_t)hip_stream;
+    c.cap = STS_STATIC_MAX_TERMS;
+    c.scap = side_capacity(c.cap);
+    c.tiles_cap = ceil_div(c.cap, STS_TILE);
+    c.gtiles_cap = ceil_div(c.cap, STS_GTILE);
+    c.mem = (unsigned char *)base;
+    bind_layout(&c, L);
+    // the array keeps the last call's contents: every counter, histogram and
+    // look-back word starts from zero again, and the control block anew
+    STS_TRY(&c, launch_fill_zero((u64 *)(c.mem + L.h1), (L.total - L.h1) / 8, c.stream));
+    STS_TRY(&c, launch_ctl_begin(c.ctl, c.K, c.p, n_in, c.stream));
+    const u64 asz = precision == STS_C128 ? 16 : 8;
+    if (n_in) {
+        STS_TRY(&c, hipMemcpyAsync(c.keys[0], keys_in, n_in * 8, hipMemcpyDeviceToDevice, c.stream));
+        STS_TRY(&c, hipMemcpyAsync(c.amps[0], amps_in, n_in * asz, hipMemcpyDeviceToDevice, c.stream));
+    }
+    c.cur = 0;
+    c.n_bound = n_in;
+    sts_status st = sts_apply_gate(&c, m, qubits, U);
+    if (st != STS_OK) return st;
+    st = sts_truncate(&c);
+    if (st != STS_OK) return st;
+    STS_TRY(&c, launch_terms_out(c.keys[c.cur], c.amps[c.cur], (int)asz, c.ctl, c.cur, (u64 *)keys_out, amps_out,
+                                 max_terms, (u64 *)n_out, stats, c.stream));
     return STS_OK;
 }
 

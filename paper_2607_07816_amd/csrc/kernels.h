@@ -85,6 +85,10 @@ hipError_t launch_group_emit_tiles(int prec, const GateArg &g, const PassBufs &b
 hipError_t launch_final(const PassBufs &b, hipStream_t s);
 hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s);
 hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s);
+hipError_t launch_fill_zero(u64 *p, u64 n, hipStream_t s);
+hipError_t launch_ctl_begin(DevCtl *ctl, u64 K, double p, u64 n_in, hipStream_t s);
+hipError_t launch_terms_out(const u64 *keys, const void *amps, int amp_bytes, const DevCtl *ctl, int slot,
+                            u64 *keys_out, void *amps_out, u64 out_cap, u64 *n_out, double *stats, hipStream_t s);
 
 // workgroups to launch for a compaction pass over n terms with an m-qubit
 // gate: m <= 3 uses LDS tiles of 2048 terms, larger

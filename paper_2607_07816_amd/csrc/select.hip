@@ -16,6 +16,8 @@
 // mantissas, levels >= 2 share one exponent, and level 1 prefixes are exact
 // integers on the 2^-1074 grid. Every decision therefore equals the one made
 // in exact arithmetic, and the kept mass S is correctly rounded.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace {
@@ -1008,6 +1010,54 @@ __global__ void k_init_state(u64 *keys, double2 *amps64, float2 *amps32, u64 *n_
 
 __global__ void k_set_n(u64 *n_out, u64 n) { *n_out = n; }
 
+// zero n words (a kernel rather than a memset, so the work can sit in a
+// captured graph)
+__global__ void __launch_bounds__(256) k_fill_zero(u64 *p, u64 n)
+{
+    for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < n; i += (u64)gridDim.x * 256) p[i] = 0;
+}
+
+// a fresh control block: the rule, nothing cut yet, n_in terms in buffer 0
+__global__ void __launch_bounds__(64) k_ctl_begin(DevCtl *ctl, u64 K, double p, u64 n_in)
+{
+    u64 *w = reinterpret_cast<u64 *>(ctl);
+    constexpr u64 words = sizeof(DevCtl) / sizeof(u64);
+    static_assert(sizeof(DevCtl) % sizeof(u64) == 0, "DevCtl is a whole number of words");
+    for (u64 i = threadIdx.x; i < words; i += 64) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->K = K;
+        ctl->p = p;
+        ctl->scale = 1.0;
+        ctl->frac = 1.0;
+        ctl->e_pred = -1;
+        ctl->cnt[0] = n_in;
+    }
+}
+
+// copy the cnt[slot] terms of (keys, amps) to the caller's arrays (at most
+// out_cap), their count to *n_out and, if stats is set, W and the kept
+// fraction to stats[0..1]
+__global__ void __launch_bounds__(256) k_terms_out(const u64 *keys, const void *amps, int amp_bytes,
+                                                   const DevCtl *ctl, int slot, u64 *keys_out, void *amps_out,
+                                                   u64 out_cap, u64 *n_out, double *stats)
+{
+    const u64 n0 = ctl->cnt[slot];
+    const u64 n = n0 < out_cap ? n0 : out_cap;
+    for (u64 i = (u64)blockIdx.x * 256 + threadIdx.x; i < n; i += (u64)gridDim.x * 256) {
+        keys_out[i] = keys[i];
+        if (amp_bytes == 16) reinterpret_cast<double2 *>(amps_out)[i] = reinterpret_cast<const double2 *>(amps)[i];
+        else reinterpret_cast<float2 *>(amps_out)[i] = reinterpret_cast<const float2 *>(amps)[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *n_out = n;
+        if (stats) {
+            stats[0] = ctl->W;
+            stats[1] = ctl->frac;
+        }
+    }
+}
+
 } // namespace
 
 hipError_t launch_pick1(const PassBufs &b, int groups, int peak_only, int predicted, hipStream_t s)
@@ -1060,3 +1110,25 @@ hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_zero(u64 *p, u64 n, hipStream_t s)
+{
+    const u64 blocks = std::min<u64>((n + 255) / 256, 1024);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_begin(DevCtl *ctl, u64 K, double p, u64 n_in, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_begin, dim3(1), dim3(64), 0, s, ctl, K, p, n_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_terms_out(const u64 *keys, const void *amps, int amp_bytes, const DevCtl *ctl, int slot,
+                            u64 *keys_out, void *amps_out, u64 out_cap, u64 *n_out, double *stats, hipStream_t s)
+{
+    const u64 blocks = std::max<u64>(std::min<u64>((out_cap + 255) / 256, 1024), 1);
+    hipLaunchKernelGGL(k_terms_out, dim3((unsigned)blocks), dim3(256), 0, s, keys, amps, amp_bytes, ctl, slot,
+                       keys_out, amps_out, out_cap, n_out, stats);
+    return hipGetLastError();
+}
