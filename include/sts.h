@@ -227,9 +227,11 @@ typedef struct {
     int precision;   /* STS_C128 or STS_C64, for every circuit                 */
     int n_streams;   /* circuits in flight, 1..64: each has a host thread, a   */
                      /* HIP stream and a device arena of its own               */
-    int graph_steps; /* 0: plain launches; g > 0: record up to g consecutive    */
-                     /* truncated gates of <= 3 qubits into one HIP graph and   */
-                     /* launch that                                            */
+    int graph_steps; /* 0: plain launches; > 0: a truncated gate step of up   */
+                     /* to 3 qubits (top-k on) is captured into a HIP graph    */
+                     /* once per state of the circuit's context (term buffer,  */
+                     /* size bound, gate size) and replayed for later gates    */
+                     /* with only the gate changed                             */
 } sts_batch_config;
 
 typedef struct {

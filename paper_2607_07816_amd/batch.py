@@ -3,8 +3,8 @@ autotuner for the batch runner's launch configuration.
 
 A batch item is (circuit, K, p). Every circuit runs through its own context,
 exactly as it would alone; the batch only decides how many run at once
-(`streams`) and whether runs of truncated gates are launched as HIP graphs
-(`graph_steps`).
+(`streams`) and whether truncated gate steps are captured into HIP graphs
+and replayed with the next gate (`graph_steps` > 0).
 """
 from __future__ import annotations
 

@@ -39,7 +39,7 @@ u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
     u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
-        t_above, t_side, t_off, tctr, dU, sub_cnt, wpart, sbins, total;
+        t_above, t_side, t_off, tctr, dU, sub_cnt, wpart, sbins, gate, total;
 };
 
 // tiles of the LDS-tiled passes (2048 terms each) and the side-buffer entries:
@@ -84,6 +84,7 @@ Layout make_layout(u64 cap, int prec)
     L.sub_cnt = take((STS_SUB_REGIONS + 1) * 128);
     L.wpart = take(6 * STS_MAX_GROUPS * 8);
     L.sbins = take(STS_SW_BANKS * (STS_SW_NB + 4) * 8);
+    L.gate = take(2 * sizeof(GateArg)); // the current gate, and the identity
     L.total = o;
     return L;
 }
@@ -144,6 +145,8 @@ struct sts_ctx {
     double *dU = nullptr;
     u32 *sub_cnt = nullptr;
     u64 *wpart = nullptr, *sbins = nullptr;
+    GateArg *dgate = nullptr, *dgate_id = nullptr; // device copies of the gate and of the identity
+    const GateArg *gate_dev = nullptr;              // the one the pending step's kernels read
     double *hU = nullptr;    // pinned staging of U for m >= 4
     hipEvent_t u_event = nullptr;
     bool u_event_live = false;
@@ -241,6 +244,7 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
 {
     PassBufs b;
     std::memset(&b, 0, sizeof(b));
+    b.gate = c->gate_dev;
     b.keys = c->keys[in];
     b.amps = c->amps[in];
     b.n_in = &c->ctl->cnt[in];
@@ -319,6 +323,9 @@ void bind_layout(sts_ctx *c, const Layout &L)
     c->sub_cnt = (u32 *)(c->mem + L.sub_cnt);
     c->wpart = (u64 *)(c->mem + L.wpart);
     c->sbins = (u64 *)(c->mem + L.sbins);
+    c->dgate = (GateArg *)(c->mem + L.gate);
+    c->dgate_id = c->dgate + 1;
+    c->gate_dev = c->dgate_id;
 }
 
 // copy the control block to the host and wait; map device-side error flags
@@ -353,15 +360,23 @@ sts_status refuse_step(sts_ctx *c)
     return STS_E_CAPACITY;
 }
 
-// group the state in buffer cur by the hash bucket of key & notmask; returns
-// the buffer that holds the sorted terms and the bucket bits used
-sts_status sort_state(sts_ctx *c, u64 notmask, int *sorted, int *hb_out)
+// 8-bit digit passes of the grouping sort: enough bucket bits for the
+// state's size bound
+int sort_passes(const sts_ctx *c)
 {
     const u64 nb = std::max<u64>(c->n_bound, 2);
     int lg = 0;
     while ((1ull << lg) < nb && lg < 63) ++lg;
-    int npass = (lg + 7) / 8;
-    npass = std::min(std::max(npass, 1), STS_MAX_PASSES);
+    return std::min(std::max((lg + 7) / 8, 1), STS_MAX_PASSES);
+}
+
+// group the state in buffer cur by the hash bucket of key & notmask (the
+// device gate's); returns
+// the buffer that holds the sorted terms and the bucket bits used
+sts_status sort_state(sts_ctx *c, const u64 *notmask, int *sorted, int *hb_out)
+{
+    const u64 nb = std::max<u64>(c->n_bound, 2);
+    const int npass = sort_passes(c);
     const int hb = 8 * npass;
     const int tiles = (int)std::max<u64>(ceil_div(nb, STS_TILE), 1);
     const int a = (c->cur + 1) % 3, b = (c->cur + 2) % 3;
@@ -430,6 +445,50 @@ sts_status materialise(sts_ctx *c)
     c->cur = dst;
     c->n_bound = std::min(bound, c->cap);
     c->pending = false;
+    return STS_OK;
+}
+
+// the gate's kernel description (everything but the bucket bits hb, and
+// for m >= 4 the device pointer to U); qubits and U already checked
+void fill_gate(GateArg *g, int m, const int *qubits, const double *U)
+{
+    std::memset(g, 0, sizeof(*g));
+    g->m = m;
+    u64 mask = 0;
+    for (int t = 0; t < m; ++t) {
+        g->q[t] = qubits[t];
+        mask |= 1ull << qubits[t];
+    }
+    g->notmask = ~mask;
+    const int dim = 1 << m;
+    if (m <= 3) {
+        for (int i = 0; i < dim * dim; ++i) {
+            g->ur[i] = U[2 * i];
+            g->ui[i] = U[2 * i + 1];
+            g->fr[i] = (float)U[2 * i]; // nearest-even
+            g->fi[i] = (float)U[2 * i + 1];
+        }
+        for (int i = 0; i < dim; ++i) {
+            u64 d = 0;
+            for (int t = 0; t < m; ++t)
+                if ((i >> t) & 1) d |= 1ull << qubits[t];
+            g->dep[i] = d;
+        }
+    }
+}
+
+// STS_E_ARG unless qubits are m distinct qubits of the state and U is finite
+sts_status check_gate(const sts_ctx *c, int m, const int *qubits, const double *U)
+{
+    if (!qubits || !U || m < 1 || m > STS_MAXM || m > c->n_qubits) return STS_E_ARG;
+    u64 mask = 0;
+    for (int t = 0; t < m; ++t) {
+        if (qubits[t] < 0 || qubits[t] >= c->n_qubits) return STS_E_ARG;
+        if (mask & (1ull << qubits[t])) return STS_E_ARG;
+        mask |= 1ull << qubits[t];
+    }
+    for (int i = 0; i < 2 << (2 * m); ++i)
+        if (!std::isfinite(U[i])) return STS_E_ARG;
     return STS_OK;
 }
 
@@ -535,6 +594,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     e = hipMemsetAsync(c->mem + L.h1, 0, L.total - L.h1, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->ctl, c->hctl, sizeof(DevCtl), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_init_state(precision, c->keys[0], c->amps[0], &c->ctl->cnt[0], c->stream);
+    if (e == hipSuccess) e = launch_set_gate(identity_gate(), c->dgate_id, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         sts_free(c);
@@ -550,38 +610,15 @@ sts_status sts_apply_gate(sts_ctx *c, int m, const int *qubits, const double *U)
 {
     sts_status st = check_live(c);
     if (st != STS_OK) return st;
-    if (!qubits || !U || m < 1 || m > STS_MAXM || m > c->n_qubits) return STS_E_ARG;
-    u64 mask = 0;
-    for (int t = 0; t < m; ++t) {
-        if (qubits[t] < 0 || qubits[t] >= c->n_qubits) return STS_E_ARG;
-        if (mask & (1ull << qubits[t])) return STS_E_ARG;
-        mask |= 1ull << qubits[t];
-    }
-    for (int i = 0; i < 2 << (2 * m); ++i)
-        if (!std::isfinite(U[i])) return STS_E_ARG;
+    st = check_gate(c, m, qubits, U);
+    if (st != STS_OK) return st;
     st = materialise(c);
     if (st != STS_OK) return st;
 
     GateArg g;
-    std::memset(&g, 0, sizeof(g));
-    g.m = m;
-    for (int t = 0; t < m; ++t) g.q[t] = qubits[t];
-    g.notmask = ~mask;
+    fill_gate(&g, m, qubits, U);
     const int dim = 1 << m;
-    if (m <= 3) {
-        for (int i = 0; i < dim * dim; ++i) {
-            g.ur[i] = U[2 * i];
-            g.ui[i] = U[2 * i + 1];
-            g.fr[i] = (float)U[2 * i]; // nearest-even
-            g.fi[i] = (float)U[2 * i + 1];
-        }
-        for (int i = 0; i < dim; ++i) {
-            u64 d = 0;
-            for (int t = 0; t < m; ++t)
-                if ((i >> t) & 1) d |= 1ull << qubits[t];
-            g.dep[i] = d;
-        }
-    } else {
+    if (m > 3) {
         // the previous copy from the staging buffer must have finished
         if (c->u_event_live) STS_TRY(c, hipEventSynchronize(c->u_event));
         std::memcpy(c->hU, U, (size_t)2 * dim * dim * sizeof(double));
@@ -592,9 +629,11 @@ sts_status sts_apply_gate(sts_ctx *c, int m, const int *qubits, const double *U)
         g.uptr = c->dU;
     }
     int sorted = c->cur, hb = 8;
-    st = sort_state(c, g.notmask, &sorted, &hb);
+    g.hb = 8 * sort_passes(c); // the bucket bits the sort below uses
+    STS_TRY(c, launch_set_gate(g, c->dgate, c->stream));
+    c->gate_dev = c->dgate;
+    st = sort_state(c, &c->dgate->notmask, &sorted, &hb);
     if (st != STS_OK) return st;
-    g.hb = hb;
     c->cur = sorted;
     c->gate = g;
     c->pending = true;
@@ -607,6 +646,7 @@ sts_status sts_truncate(sts_ctx *c)
     if (st != STS_OK) return st;
     if (!c->pending) {
         c->gate = identity_gate();
+        c->gate_dev = c->dgate_id;
         c->pending = true;
     }
     const u64 cb = sat_shl(c->n_bound, c->gate.m);
@@ -687,6 +727,7 @@ sts_status sts_peak(sts_ctx *c, uint64_t *key, double *prob)
     if (st != STS_OK) return st;
     const GateArg g = identity_gate();
     PassBufs b = pass_bufs(c, c->cur, -1);
+    b.gate = c->dgate_id;
     const int G = hist_groups(c->prec, c->n_bound, 0, true);
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, g, b, G, true, c->stream));
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 1, 0, c->stream));
@@ -863,6 +904,7 @@ sts_status sts_step_static(int n_qubits, uint64_t max_terms, double mass, int pr
     // look-back word starts from zero again, and the control block anew
     STS_TRY(&c, launch_fill_zero((u64 *)(c.mem + L.h1), (L.total - L.h1) / 8, c.stream));
     STS_TRY(&c, launch_ctl_begin(c.ctl, c.K, c.p, n_in, c.stream));
+    STS_TRY(&c, launch_set_gate(identity_gate(), c.dgate_id, c.stream));
     const u64 asz = precision == STS_C128 ? 16 : 8;
     if (n_in) {
         STS_TRY(&c, hipMemcpyAsync(c.keys[0], keys_in, n_in * 8, hipMemcpyDeviceToDevice, c.stream));
@@ -909,3 +951,130 @@ const char *sts_strerror(sts_status s)
 }
 
 } // extern "C"
+
+// ---------------------------------------------------------------------------
+// Replayed gate steps (batch runner). A truncated step of up to 3 qubits
+// launches the same kernels with the same grids whenever the context starts
+// it from the same term buffer with the same size bound: every size the
+// kernels use is read from device memory, and the gate itself from the
+// context's device copy, written by one k_set_gate launch. Such a step is
+// captured into a HIP graph once and afterwards replayed with only that
+// launch's argument changed to the new gate.
+// ---------------------------------------------------------------------------
+struct StepGraph {
+    int m, cur;
+    u64 nb;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipGraphNode_t set_node;
+    int cur_after;
+    u64 nb_after;
+};
+
+struct StepGraphs {
+    std::vector<StepGraph> v;
+    u64 last_nb = ~0ull;
+    u64 replays = 0, captures = 0;
+};
+
+StepGraphs *step_graphs_new() { return new (std::nothrow) StepGraphs(); }
+
+void step_graphs_free(StepGraphs *gs)
+{
+    if (!gs) return;
+    for (auto &e : gs->v) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
+    delete gs;
+}
+
+void step_graphs_counts(const StepGraphs *gs, u64 *captures, u64 *replays)
+{
+    *captures = gs ? gs->captures : 0;
+    *replays = gs ? gs->replays : 0;
+}
+
+sts_status step_replayed(sts_ctx *c, StepGraphs *gs, int m, const int *qubits, const double *U)
+{
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    st = check_gate(c, m, qubits, U);
+    if (st != STS_OK) return st;
+    // a steady size bound (as the previous step's) and a step that never
+    // synchronises: gates of up to 3 qubits, top-k within the capacity
+    const bool steady = c->n_bound == gs->last_nb;
+    gs->last_nb = c->n_bound;
+    if (!steady || c->pending || c->prof || m > 3 || c->K == 0 || c->K > c->cap) {
+        st = sts_apply_gate(c, m, qubits, U);
+        if (st == STS_OK) st = sts_truncate(c);
+        return st;
+    }
+    StepGraph *hit = nullptr;
+    for (auto &e : gs->v)
+        if (e.m == m && e.cur == c->cur && e.nb == c->n_bound) hit = &e;
+    if (!hit) {
+        StepGraph e{};
+        e.m = m;
+        e.cur = c->cur;
+        e.nb = c->n_bound;
+        STS_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        st = sts_apply_gate(c, m, qubits, U);
+        if (st == STS_OK) st = sts_truncate(c);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+        if (st != STS_OK || ee != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            c->poisoned = true; // the step was recorded, not run
+            return st != STS_OK ? st : STS_E_HIP;
+        }
+        e.graph = graph;
+        e.cur_after = c->cur;
+        e.nb_after = c->n_bound;
+        // the one launch that writes the gate
+        size_t nn = 0;
+        hipError_t he = hipGraphGetNodes(graph, nullptr, &nn);
+        std::vector<hipGraphNode_t> nodes(nn);
+        if (he == hipSuccess) he = hipGraphGetNodes(graph, nodes.data(), &nn);
+        for (size_t i = 0; he == hipSuccess && i < nn; ++i) {
+            hipGraphNodeType t;
+            if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+            hipKernelNodeParams p{};
+            if (hipGraphKernelNodeGetParams(nodes[i], &p) == hipSuccess && p.func == set_gate_kernel())
+                e.set_node = nodes[i];
+        }
+        if (he == hipSuccess && !e.set_node) he = hipErrorNotFound;
+        if (he == hipSuccess) he = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+        if (he == hipSuccess) he = hipGraphLaunch(e.exec, c->stream);
+        if (he != hipSuccess) {
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+            (void)hipGraphDestroy(graph);
+            return fail_hip(c, he);
+        }
+        gs->v.push_back(e);
+        gs->captures += 1;
+        return STS_OK;
+    }
+    // replay with the new gate: the same bucket bits (same size bound)
+    GateArg g;
+    fill_gate(&g, m, qubits, U);
+    g.hb = 8 * sort_passes(c);
+    GateArg *dst = c->dgate;
+    void *args[2] = {&g, &dst};
+    hipKernelNodeParams p{};
+    p.func = const_cast<void *>(set_gate_kernel());
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(64);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    STS_TRY(c, hipGraphExecKernelNodeSetParams(hit->exec, hit->set_node, &p));
+    STS_TRY(c, hipGraphLaunch(hit->exec, c->stream));
+    c->cur = hit->cur_after;
+    c->n_bound = hit->nb_after;
+    c->gate = g;
+    c->gate_dev = c->dgate;
+    c->pending = false;
+    gs->replays += 1;
+    return STS_OK;
+}

@@ -7,9 +7,10 @@
 // device arena, and runs whole circuits through an ordinary context carved
 // from that arena, so every circuit computes exactly what it computes alone.
 // Circuits are handed out longest first (work ~ gates x min(K, 2^n)).
-// Optionally, runs of consecutive truncated gates (m <= 3) are captured into a
-// HIP graph and launched as one, which replaces a dozen launch calls per gate
-// by one graph launch per chunk.
+// Optionally, truncated gate steps of up to 3 qubits are captured into HIP
+// graphs, one per state of the context (term buffer, size bound, gate size),
+// and replayed with only the gate changed: one graph launch per gate instead
+// of a dozen kernel launches.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -28,18 +29,6 @@ struct BatchJob {
     double work;
 };
 
-struct Graphs {
-    std::vector<hipGraph_t> g;
-    std::vector<hipGraphExec_t> x;
-    void clear()
-    {
-        for (auto e : x) (void)hipGraphExecDestroy(e);
-        for (auto h : g) (void)hipGraphDestroy(h);
-        x.clear();
-        g.clear();
-    }
-};
-
 // one circuit start to finish on an existing stream and arena
 void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, void *arena, size_t arena_bytes,
              sts_circuit_result *r)
@@ -48,54 +37,25 @@ void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, voi
     std::memset(r, 0, sizeof(*r));
     sts_ctx *ctx = nullptr;
     sts_status st = sts_init(&ctx, c.n_qubits, c.max_terms, c.mass, prec, s, arena, arena_bytes, circuit_cap(c));
-    Graphs graphs;
+    StepGraphs *gs = graph_steps > 0 && st == STS_OK ? step_graphs_new() : nullptr;
     u64 qo = 0, uo = 0;
     u64 i = 0;
-    bool prev_truncated = true;
     while (st == STS_OK && i < c.n_gates) {
         const int m = c.gate_m[i];
-        const bool capturable = graph_steps > 0 && c.max_terms > 0 && m <= 3 && c.truncate_after[i] &&
-                                prev_truncated;
-        if (!capturable) {
-            prev_truncated = c.truncate_after[i] != 0;
+        if (!gs || m > 3 || !c.truncate_after[i] || c.max_terms == 0) {
             st = run_gates(ctx, c, i + 1, &i, &qo, &uo);
             continue;
         }
-        // a chunk of consecutive truncated gates of up to 3 qubits: no call in
-        // it synchronises, so the whole chunk records into one graph
-        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            st = STS_E_HIP;
-            break;
-        }
-        int k = 0;
-        while (st == STS_OK && i < c.n_gates && k < graph_steps && c.gate_m[i] <= 3 && c.truncate_after[i]) {
-            const int mi = c.gate_m[i];
-            st = sts_apply_gate(ctx, mi, c.gate_qubits + qo, c.gate_U + uo);
-            if (st == STS_OK) st = sts_truncate(ctx);
-            qo += (u64)mi;
-            uo += 2ull << (2 * mi);
-            ++i;
-            ++k;
-        }
-        hipGraph_t gr = nullptr;
-        e = hipStreamEndCapture(s, &gr);
-        if (st != STS_OK || e != hipSuccess || !gr) {
-            if (gr) (void)hipGraphDestroy(gr);
-            if (st == STS_OK) st = STS_E_HIP;
-            break;
-        }
-        hipGraphExec_t ex = nullptr;
-        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(ex, s);
-        graphs.g.push_back(gr);
-        if (ex) graphs.x.push_back(ex);
-        if (e != hipSuccess) st = STS_E_HIP;
-        prev_truncated = true;
+        // truncated steps of up to 3 qubits: captured once per state of the
+        // context, then replayed
+        st = step_replayed(ctx, gs, m, c.gate_qubits + qo, c.gate_U + uo);
+        qo += (u64)m;
+        uo += 2ull << (2 * m);
+        ++i;
     }
     if (st == STS_OK) st = finish(ctx, c, r);
     if (ctx) sts_free(ctx); // waits for the stream
-    graphs.clear();
+    step_graphs_free(gs);
     r->status = st;
     r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     r->latency_seconds = r->seconds;

@@ -187,8 +187,9 @@ template <typename AT> __device__ __forceinline__ u64 weight_bits(AT a)
 // mantissa sums, plus each workgroup's best term (weight desc, key asc)
 // ---------------------------------------------------------------------------
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG) k_group_hist(GateArg g, PassBufs b)
+__global__ void __launch_bounds__(STS_WG) k_group_hist(const GateArg *__restrict__ gp, PassBufs b)
 {
+    const GateArg &g = *gp;
     __shared__ u32 s_cnt[STS_NBIN];
     __shared__ u64 s_hi[STS_NBIN];
     __shared__ u64 s_lo[STS_NBIN];
@@ -281,8 +282,9 @@ __device__ __forceinline__ bool keep_out(const DevCtl *ctl, int materialise, con
 }
 
 template <typename AT, int M, int KIND>
-__global__ void __launch_bounds__(STS_WG) k_group_compact(GateArg g, PassBufs b)
+__global__ void __launch_bounds__(STS_WG) k_group_compact(const GateArg *__restrict__ gp, PassBufs b)
 {
+    const GateArg &g = *gp;
     typedef typename Scalar<AT>::T R;
     constexpr int IT = STS_GROUP_ITEMS;
     __shared__ u32 s_tile;
@@ -616,8 +618,9 @@ __device__ __forceinline__ void flush_window(u64 *s_wacc, u64 &ma, u64 &mw)
 // tile's candidates above it are counted: when this step's cut exponent turns
 // out the same, the extraction pass has nothing left to do.
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
+__global__ void __launch_bounds__(STS_WG) k_tile_hist(const GateArg *__restrict__ gp, PassBufs b)
 {
+    const GateArg &g = *gp;
     __shared__ TileSmem<AT> s;
     __shared__ u64 s_hi[TT_COPIES * TT_NB]; // sum of mantissa >> 26
     __shared__ u64 s_lo[TT_COPIES * TT_NB]; // sum of mantissa & (2^26-1), plus count << 44
@@ -810,8 +813,9 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(GateArg g, PassBufs b)
 // nothing).
 // ---------------------------------------------------------------------------
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG) k_tile_sample(GateArg g, PassBufs b)
+__global__ void __launch_bounds__(STS_WG) k_tile_sample(const GateArg *__restrict__ gp, PassBufs b)
 {
+    const GateArg &g = *gp;
     constexpr int SPAN = STS_SAMPLE_SPAN; // inputs per workgroup, from a tile's start
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_c[STS_SW_NB];
@@ -981,8 +985,9 @@ __global__ void __launch_bounds__(STS_WG) k_tile_sample(GateArg g, PassBufs b)
 //   k_tile_emit    - writes the tile's survivors at its offset
 // ---------------------------------------------------------------------------
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG) k_tile_extract(GateArg g, PassBufs b)
+__global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restrict__ gp, PassBufs b)
 {
+    const GateArg &g = *gp;
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_above, s_side;
     const int tid = threadIdx.x;
@@ -1049,8 +1054,9 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(GateArg g, PassBufs b)
 }
 
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG) k_tile_emit(GateArg g, PassBufs b)
+__global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict__ gp, PassBufs b)
 {
+    const GateArg &g = *gp;
     typedef typename Scalar<AT>::T R;
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_out;
@@ -1131,8 +1137,8 @@ template <typename AT, int M, bool TILED> int hist_capacity()
 template <typename AT, int M, bool TILED>
 hipError_t hist_m(const GateArg &g, const PassBufs &b, int grid, hipStream_t s)
 {
-    if constexpr (TILED) hipLaunchKernelGGL((k_tile_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
-    else hipLaunchKernelGGL((k_group_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, g, b);
+    if constexpr (TILED) hipLaunchKernelGGL((k_tile_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, b.gate, b);
+    else hipLaunchKernelGGL((k_group_hist<AT, M>), dim3(grid), dim3(STS_WG), 0, s, b.gate, b);
     return hipGetLastError();
 }
 
@@ -1140,27 +1146,27 @@ template <typename AT, int M>
 hipError_t compact_m(int kind, const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
     if (kind == STS_KIND_EXTRACT)
-        hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EXTRACT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+        hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EXTRACT>), dim3(tiles), dim3(STS_WG), 0, s, b.gate, b);
     else
-        hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EMIT>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+        hipLaunchKernelGGL((k_group_compact<AT, M, STS_KIND_EMIT>), dim3(tiles), dim3(STS_WG), 0, s, b.gate, b);
     return hipGetLastError();
 }
 
 template <typename AT, int M> hipError_t extract_tiles_m(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tile_extract<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+    hipLaunchKernelGGL((k_tile_extract<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, b.gate, b);
     return hipGetLastError();
 }
 
 template <typename AT, int M> hipError_t sample_m(const GateArg &g, const PassBufs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tile_sample<AT, M>), dim3(STS_SAMPLE_TILES), dim3(STS_WG), 0, s, g, b);
+    hipLaunchKernelGGL((k_tile_sample<AT, M>), dim3(STS_SAMPLE_TILES), dim3(STS_WG), 0, s, b.gate, b);
     return hipGetLastError();
 }
 
 template <typename AT, int M> hipError_t emit_tiles_m(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_tile_emit<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, g, b);
+    hipLaunchKernelGGL((k_tile_emit<AT, M>), dim3(tiles), dim3(STS_WG), 0, s, b.gate, b);
     return hipGetLastError();
 }
 

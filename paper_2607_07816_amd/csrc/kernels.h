@@ -26,6 +26,7 @@ struct GateArg {
 
 // Device buffers a grouping pass reads and writes.
 struct PassBufs {
+    const GateArg *gate;  // the gate (device memory: written by k_set_gate per gate)
     const u64 *keys;      // sorted input keys (or the state, m = 0)
     const void *amps;     // sorted input amplitudes
     const u64 *n_in;      // number of input terms (device)
@@ -62,12 +63,12 @@ struct PassBufs {
 };
 
 // launch helpers (return hipError_t of the launch)
-hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, u64 notmask, int shift, u32 *counts,
+hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, const u64 *notmask, int shift, u32 *counts,
                               u64 tiles_cap, int tiles, hipStream_t s);
 hipError_t launch_radix_scan(const u32 *counts, u64 *prefix, u64 *totals, const u64 *n_in, u64 tiles_cap,
                              hipStream_t s);
 hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout, const u64 *n_in,
-                             u64 *n_out, u64 notmask, int shift, const u64 *prefix, const u64 *totals,
+                             u64 *n_out, const u64 *notmask, int shift, const u64 *prefix, const u64 *totals,
                              u64 tiles_cap, int tiles, hipStream_t s);
 
 hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, bool tiled, hipStream_t s);
@@ -85,6 +86,8 @@ hipError_t launch_group_emit_tiles(int prec, const GateArg &g, const PassBufs &b
 hipError_t launch_final(const PassBufs &b, hipStream_t s);
 hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStream_t s);
 hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s);
+hipError_t launch_set_gate(const GateArg &g, GateArg *dst, hipStream_t s);
+const void *set_gate_kernel(); // the kernel launch_set_gate launches (to find its node in a captured graph)
 hipError_t launch_fill_zero(u64 *p, u64 n, hipStream_t s);
 hipError_t launch_ctl_begin(DevCtl *ctl, u64 K, double p, u64 n_in, hipStream_t s);
 hipError_t launch_terms_out(const u64 *keys, const void *amps, int amp_bytes, const DevCtl *ctl, int slot,

@@ -32,11 +32,13 @@ __device__ __forceinline__ u32 bucket_digit(u64 key, u64 notmask, int shift)
 }
 
 // digit counts of one tile, written digit-major: counts[d * tiles_cap + tile]
-__global__ void __launch_bounds__(STS_WG) k_radix_count(const u64 *__restrict__ keys, const u64 *n_in, u64 notmask,
-                                                         int shift, u32 *__restrict__ counts, u64 tiles_cap)
+__global__ void __launch_bounds__(STS_WG) k_radix_count(const u64 *__restrict__ keys, const u64 *n_in,
+                                                         const u64 *gate_notmask, int shift, u32 *__restrict__ counts,
+                                                         u64 tiles_cap)
 {
     __shared__ u32 s_h[256];
     const u64 n = *n_in;
+    const u64 notmask = *gate_notmask;
     // the state's tiles go to the XCDs in contiguous ranges, so that the
     // counts of neighbouring tiles (adjacent in each digit's row) are written
     // through one L2; workgroups past the state's tiles write zeros
@@ -130,10 +132,11 @@ __global__ void __launch_bounds__(STS_WG) k_radix_scan(const u32 *__restrict__ c
 template <int W>
 __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ kin, const u64 *__restrict__ ain,
                                                         u64 *__restrict__ kout, u64 *__restrict__ aout,
-                                                        const u64 *n_in, u64 *n_out, u64 notmask, int shift,
-                                                        const u64 *__restrict__ prefix,
+                                                        const u64 *n_in, u64 *n_out, const u64 *gate_notmask,
+                                                        int shift, const u64 *__restrict__ prefix,
                                                         const u64 *__restrict__ totals, u64 tiles_cap)
 {
+    const u64 notmask = *gate_notmask;
     constexpr int NW = STS_WG / 64;
     constexpr int IT = STS_TILE_ITEMS;
     constexpr int ESZ = 8 * W;
@@ -275,7 +278,7 @@ __global__ void __launch_bounds__(STS_WG) k_radix_pass(const u64 *__restrict__ k
 
 } // namespace
 
-hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, u64 notmask, int shift, u32 *counts,
+hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, const u64 *notmask, int shift, u32 *counts,
                               u64 tiles_cap, int tiles, hipStream_t s)
 {
     hipLaunchKernelGGL(k_radix_count, dim3(tiles), dim3(STS_WG), 0, s, keys, n_in, notmask, shift, counts, tiles_cap);
@@ -290,7 +293,7 @@ hipError_t launch_radix_scan(const u32 *counts, u64 *prefix, u64 *totals, const 
 }
 
 hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout, const u64 *n_in,
-                             u64 *n_out, u64 notmask, int shift, const u64 *prefix, const u64 *totals,
+                             u64 *n_out, const u64 *notmask, int shift, const u64 *prefix, const u64 *totals,
                              u64 tiles_cap, int tiles, hipStream_t s)
 {
     static_assert(sizeof(double2) == 2 * sizeof(u64) && sizeof(float2) == sizeof(u64), "amplitude words");

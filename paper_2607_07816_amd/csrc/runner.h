@@ -6,6 +6,16 @@
 #include "sts.h"
 #include "kernels.h"
 
+// replayed gate steps (api.hip): a per-context cache of captured steps
+struct StepGraphs;
+StepGraphs *step_graphs_new();
+void step_graphs_free(StepGraphs *gs);
+void step_graphs_counts(const StepGraphs *gs, u64 *captures, u64 *replays);
+// one truncated gate step, as sts_apply_gate + sts_truncate; replayed from a
+// captured graph when the context starts it in the state of an earlier step
+// (same term buffer, same size bound, same gate size)
+sts_status step_replayed(sts_ctx *c, StepGraphs *gs, int m, const int *qubits, const double *U);
+
 namespace sts_runner {
 
 inline bool circuit_valid(const sts_circuit &c)

@@ -1010,6 +1010,17 @@ __global__ void k_init_state(u64 *keys, double2 *amps64, float2 *amps32, u64 *n_
 
 __global__ void k_set_n(u64 *n_out, u64 n) { *n_out = n; }
 
+// the gate's description into device memory, where every kernel of its step
+// reads it (a captured step is replayed for another gate by changing this
+// one launch's argument)
+__global__ void __launch_bounds__(64) k_set_gate(GateArg g, GateArg *dst)
+{
+    static_assert(sizeof(GateArg) % sizeof(u32) == 0, "GateArg is a whole number of words");
+    const u32 *src = reinterpret_cast<const u32 *>(&g);
+    u32 *d = reinterpret_cast<u32 *>(dst);
+    for (u32 i = threadIdx.x; i < sizeof(GateArg) / sizeof(u32); i += 64) d[i] = src[i];
+}
+
 // zero n words (a kernel rather than a memset, so the work can sit in a
 // captured graph)
 __global__ void __launch_bounds__(256) k_fill_zero(u64 *p, u64 n)
@@ -1103,6 +1114,14 @@ hipError_t launch_init_state(int prec, u64 *keys, void *amps, u64 *n_out, hipStr
                        prec == 0 ? nullptr : (float2 *)amps, n_out);
     return hipGetLastError();
 }
+
+hipError_t launch_set_gate(const GateArg &g, GateArg *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_gate, dim3(1), dim3(64), 0, s, g, dst);
+    return hipGetLastError();
+}
+
+const void *set_gate_kernel() { return reinterpret_cast<const void *>(&k_set_gate); }
 
 hipError_t launch_set_n(u64 *n_out, u64 n, hipStream_t s)
 {

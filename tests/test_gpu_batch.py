@@ -86,3 +86,28 @@ def test_batch_uneven_sizes_and_order():
     for (c, K, p), r in zip(items[::-1], res):
         ref = alone(c, K, p, "c64")
         assert r["peak_key"] == ref["peak_key"] and r["n_terms"] == ref["n_terms"]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_replayed_steps_equal_eager_at_every_checkpoint(prec):
+    # with graph_steps > 0 the batch runner captures a truncated step once per
+    # state of its context and replays it with the next gate; prefixes of one
+    # circuit end at different replays, and each prefix's final terms must be
+    # bit for bit those of the same prefix run eagerly
+    from paper_2607_07816_amd.circuits import Circuit
+    base = C.peaked_circuit(14, 6, 0.02, 77, pairs="random", u3_layers=False)
+    K = 300
+    lengths = [4, 9, 15, 23, 31, 40, 52, len(base.gates)]
+    items = []
+    for L in lengths:
+        c = Circuit(base.n, base.gates[:L], base.truncate_after[:L], base.hidden, base.seed, f"prefix{L}")
+        items.append((c, K, 0.0))
+    res, _ = B.run_batch(items, prec, 2, 1, want_terms=True)
+    for (c, K_, p), r in zip(items, res):
+        st = run_circuit(c, K=K_, p=p, precision=prec, capacity=1024)
+        k, a = st.read_terms()
+        st.close()
+        assert r["status"] == 0
+        assert np.array_equal(r["keys"], k), c.name
+        assert np.array_equal(r["amps"].view(np.uint64), a.view(np.uint64)), c.name
+    say(f"[batch] replayed prefixes {lengths} equal the eager runs ({prec})")
