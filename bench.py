@@ -74,7 +74,8 @@ def parse():
                          "continuous batching against the plain loop; copy: the device's streaming ceiling")
     ap.add_argument("--max-warmup", type=int, default=200,
                     help="most warm-up steps spent waiting for the state to reach its steady size")
-    ap.add_argument("--requests", type=int, default=48, help="requests of the c5 workload")
+    ap.add_argument("--requests", type=int, default=1000, help="requests of the c5 workload")
+    ap.add_argument("--spec-rate", type=float, default=200.0, help="c5: the specified arrival rate (req/s)")
     ap.add_argument("--load", type=float, default=0.7, help="c5 offered load, as a fraction of served capacity")
     ap.add_argument("--batch", type=int, default=256, help="circuits of the c4 workload")
     ap.add_argument("--fuse", type=int, default=0, metavar="M",
@@ -329,15 +330,18 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def serve_run(items, arrivals, streams, active, turn, hbm):
+def serve_run(items, arrivals, streams, active, turn, hbm, sample_every=0.5):
     """Submit items at the given arrival times (seconds from start) to a
-    fresh server; returns (results in item order, makespan seconds)."""
+    fresh server; returns (results in item order, makespan seconds, samples
+    of the server's queue [(t, queued, active, done)] every sample_every s)."""
     import threading
 
     from paper_2607_07816_amd.serve import Server
 
+    samples = []
     with Server("c64", streams, active, turn, hbm_bytes=hbm) as srv:
         tickets = [None] * len(items)
+        stop = threading.Event()
         t0 = time.perf_counter()
 
         def submitter():
@@ -347,18 +351,41 @@ def serve_run(items, arrivals, streams, active, turn, hbm):
                     time.sleep(d)
                 tickets[i] = srv.submit(c, K, p)
 
+        def monitor():
+            last = time.perf_counter()
+            while not stop.wait(sample_every):
+                st = srv.stats()
+                now = time.perf_counter()
+                samples.append((now - t0, st["queued"], st["active"], st["done"]))
+                if now - last >= 15.0:  # a progress line now and then
+                    log(f"  t={now - t0:.0f}s queued {st['queued']} active {st['active']} done {st['done']}")
+                    last = now
+
         th = threading.Thread(target=submitter)
         th.start()
+        mon = threading.Thread(target=monitor)
+        mon.start()
         th.join()
         res = [srv.wait(t) for t in tickets]
         span = time.perf_counter() - t0
-    return res, span
+        stop.set()
+        mon.join()
+    return res, span, samples
 
 
 def bench_serve(args):
-    """Poisson arrivals of uneven requests, served with continuous batching,
-    against the plain loop (one request at a time, in arrival order) fed the
-    same arrivals."""
+    """Serving (continuous batching) of Poisson arrivals of uneven requests.
+
+    1. The offered rate of the specification (--spec-rate, 200 req/s): all
+       requests arrive at that rate; the server's queue is sampled while they
+       arrive and drain, giving its served capacity (requests / makespan) and
+       how fast the queue grows at that rate.
+    2. A sustainable rate, --load (0.7) of that capacity: p50/p99 latency
+       and throughput of the server.
+    3. The plain loop (one stream, one request at a time, in arrival order)
+       fed the same arrivals as 2.
+    Every request's result must be identical in 2 and 3; its peak is also
+    compared with the circuit's hidden bit string s."""
     import numpy as np
     import torch
 
@@ -368,47 +395,67 @@ def bench_serve(args):
     t = time.perf_counter()
     ws = C.serving_workload(args.requests, 5)
     items = [(c, cfg["K"], cfg["p"]) for c, cfg in ws]
+    hidden = [c.hidden for c, _ in ws]
     log(f"{len(items)} requests generated in {time.perf_counter() - t:.1f}s "
         f"({sum(len(c.gates) for c, _, _ in items)} gates)")
-    free, _ = torch.cuda.mem_get_info()
-    hbm = int(min(free // 2, 96 << 30))
+    free, total = torch.cuda.mem_get_info()
+    # admission against the device's own memory: the server's budget is 90%
+    # of what is free on it (the rest for the runtime and torch)
+    hbm = int(free * 0.9)
+    log(f"device memory: {total / 2**30:.1f} GiB, free {free / 2**30:.1f} GiB, server budget {hbm / 2**30:.1f} GiB")
     cfg = (16, 2, 8)
-    serve_run(items[:4], [0.0] * 4, 4, 2, 8, 8 << 30)  # warm-up
-    res0, span0 = serve_run(items, [0.0] * len(items), *cfg, hbm)
-    cap_rps = len(items) / span0
-    upd = sum(r["term_updates"] for r in res0)
-    log(f"capacity probe (all at t=0): {span0:.2f}s, {cap_rps:.2f} requests/s, {upd / span0:.3e} updates/s")
-    lam = args.load * cap_rps
-    rng = np.random.default_rng(5)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(items))).tolist()
+    serve_run(items[:4], [0.0] * 4, 4, 2, 8, 8 << 30)  # warm-up: code objects, allocator
 
-    def summary(res, span):
+    def summary(res, span, arrivals):
         lat = np.array([r["latency_seconds"] for r in res])
         return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                 "mean_s": float(lat.mean()), "makespan_s": span,
+                "offered_rps": len(res) / max(arrivals[-1], 1e-9),
                 "throughput_updates_per_s": sum(r["term_updates"] for r in res) / span,
-                "throughput_requests_per_s": len(res) / span}
+                "throughput_requests_per_s": len(res) / span,
+                "peak_is_hidden": sum(int(r["peak_key"] == h) for r, h in zip(res, hidden)) / len(res)}
 
-    res_s, span_s = serve_run(items, arrivals, *cfg, hbm)
-    served = summary(res_s, span_s)
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0, size=len(items))  # unit-rate Poisson gaps, scaled per run
+    # 1. the specification's rate
+    arr_spec = np.cumsum(gaps / args.spec_rate).tolist()
+    res0, span0, samp = serve_run(items, arr_spec, *cfg, hbm)
+    cap_rps = len(items) / span0
+    t_in = arr_spec[-1]
+    during = [s_ for s_ in samp if s_[0] <= t_in] or samp[:1]
+    q_end = (during[-1][1] + during[-1][2]) if during else 0
+    spec = summary(res0, span0, arr_spec)
+    spec.update({"served_capacity_rps": cap_rps, "arrival_window_s": t_in,
+                 "backlog_at_last_arrival": int(q_end), "backlog_growth_rps": q_end / max(t_in, 1e-9),
+                 "queue_samples": [[round(a, 2), int(b), int(c_), int(d)] for a, b, c_, d in samp[:: max(1, len(samp) // 60)]]})
+    log(f"offered {spec['offered_rps']:.0f} req/s: served {cap_rps:.2f} req/s, backlog {q_end} after "
+        f"{t_in:.1f}s of arrivals ({spec['backlog_growth_rps']:.0f} req/s growth), p50 {spec['p50_s']:.2f}s "
+        f"p99 {spec['p99_s']:.2f}s")
+    # 2. a sustainable rate
+    lam = args.load * cap_rps
+    arrivals = np.cumsum(gaps / lam).tolist()
+    res_s, span_s, _ = serve_run(items, arrivals, *cfg, hbm)
+    served = summary(res_s, span_s, arrivals)
     log(f"served at {lam:.2f} req/s: p50 {served['p50_s']:.3f}s p99 {served['p99_s']:.3f}s, "
-        f"{served['throughput_updates_per_s']:.3e} updates/s")
-    res_p, span_p = serve_run(items, arrivals, 1, 1, 1 << 30, hbm)
-    plain = summary(res_p, span_p)
+        f"{served['throughput_updates_per_s']:.3e} updates/s, peak = s for {served['peak_is_hidden']:.1%}")
+    # 3. the plain loop on the same arrivals
+    res_p, span_p, _ = serve_run(items, arrivals, 1, 1, 1 << 30, hbm)
+    plain = summary(res_p, span_p, arrivals)
     log(f"plain loop at {lam:.2f} req/s: p50 {plain['p50_s']:.3f}s p99 {plain['p99_s']:.3f}s, "
         f"{plain['throughput_updates_per_s']:.3e} updates/s")
-    same = all(all(a[f] == b[f] for f in ("peak_key", "peak_prob", "n_terms", "term_updates", "log10_cum_kept"))
-               for a, b in zip(res_s, res_p))
-    log(f"served results identical to the plain loop: {same}")
-    if not same:
-        raise SystemExit("served results differ from the plain loop")
+    fields = ("peak_key", "peak_prob", "n_terms", "term_updates", "log10_cum_kept")
+    same = all(all(a[f] == b[f] for f in fields) for a, b in zip(res_s, res_p))
+    same0 = all(all(a[f] == b[f] for f in fields) for a, b in zip(res_s, res0))
+    log(f"results identical served vs plain loop: {same}; vs the spec-rate run: {same0}")
+    if not (same and same0):
+        raise SystemExit("served results differ between runs")
     line = {
         "metric": "gate-term updates/s",
         "value": served["throughput_updates_per_s"],
         "unit": "updates/s",
         "n_gpus": 1,
         "steps": sum(r["gate_steps"] for r in res_s),
-        "warmup": 0,
+        "warmup": 4,
         "ms_per_step": span_s / max(sum(r["gate_steps"] for r in res_s), 1) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -417,10 +464,12 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": f"serve{len(items)}_poisson_n20-64_K2^14-2^22_topk-or-p0.99_c64",
                    "requests": len(items), "offered_rps": lam, "load_fraction": args.load,
-                   "streams": cfg[0], "max_active": cfg[1], "gates_per_turn": cfg[2], "hbm_budget_bytes": hbm},
+                   "spec_rate_rps": args.spec_rate, "streams": cfg[0], "max_active": cfg[1],
+                   "gates_per_turn": cfg[2], "hbm_budget_bytes": hbm, "device_bytes": total},
         "served": served,
         "plain_loop": plain,
-        "capacity_probe": {"makespan_s": span0, "requests_per_s": cap_rps},
+        "spec_rate": spec,
+        "speedup_vs_plain": served["throughput_updates_per_s"] / plain["throughput_updates_per_s"],
         "roofline": None,
         "cpu_baseline": None,
     }
