@@ -570,31 +570,48 @@ template <int BITS> __device__ __forceinline__ u32 wave_claim_n(u32 cnt, u32 *co
     return base + pre;
 }
 
-// LDS bins of the histogram pass: TT_NB exponent fields from TT_EBASE, in
-// TT_COPIES copies (lane % TT_COPIES picks one) so that lanes hitting the same
-// hot exponent do not all serialise on one address; the copies of a bin are
-// adjacent, so they also fall in different LDS banks
-constexpr int TT_COPIES = 2;
+// LDS bins of the histogram pass: one per exponent field of
+// [TT_EBASE, TT_EBASE + TT_NB) ("cold"), and for the TT_HOT exponent fields
+// where most candidates land (from hot_lo: the predicted cut's exponent and
+// the ones below it) TT_HSUB sub-bins by the top fraction bits, in
+// TT_HCOPIES copies (lane % TT_HCOPIES). Lanes whose weights share a hot
+// exponent then spread over TT_HSUB * TT_HCOPIES addresses instead of
+// queuing on one; the sub-bins of an exponent are added up when flushed.
+constexpr int TT_HOT = 16, TT_HSUB = 4, TT_HCOPIES = 2;
+constexpr int TT_HPER = TT_HSUB * TT_HCOPIES;          // slots per hot exponent
+constexpr int TT_SLOTS = TT_NB + TT_HOT * TT_HPER;     // 256
+
+__device__ __forceinline__ void flush_one(const PassBufs &b, int e, u64 hi, u64 lo)
+{
+    const u64 cnt = lo >> 44;
+    if (cnt) {
+        atomicAdd(&b.h1[e], cnt);
+        atomicAdd(&b.h1[STS_NBIN + e], hi);
+        atomicAdd(&b.h1[2 * STS_NBIN + e], lo & ((1ull << 44) - 1));
+    }
+}
 
 // add the LDS bins to the global exponent histogram and clear them
-__device__ __forceinline__ void flush_bins(const PassBufs &b, u64 *s_hi, u64 *s_lo)
+__device__ __forceinline__ void flush_bins(const PassBufs &b, u64 *s_hi, u64 *s_lo, int hot_lo)
 {
     for (int i = threadIdx.x; i < TT_NB; i += STS_WG) {
+        const u64 hi = s_hi[i], lo = s_lo[i];
+        s_hi[i] = 0;
+        s_lo[i] = 0;
+        flush_one(b, TT_EBASE + i, hi, lo);
+    }
+    if (threadIdx.x < TT_HOT) {
         u64 hi = 0, lo = 0;
+        const int at = TT_NB + (int)threadIdx.x * TT_HPER;
 #pragma unroll
-        for (int c = 0; c < TT_COPIES; ++c) {
-            hi += s_hi[i * TT_COPIES + c];
-            lo += s_lo[i * TT_COPIES + c];
-            s_hi[i * TT_COPIES + c] = 0;
-            s_lo[i * TT_COPIES + c] = 0;
+        for (int k = 0; k < TT_HPER; ++k) {
+            hi += s_hi[at + k];
+            lo += s_lo[at + k];
+            s_hi[at + k] = 0;
+            s_lo[at + k] = 0;
         }
-        const u64 cnt = lo >> 44;
-        if (cnt) {
-            const int e_ = TT_EBASE + i;
-            atomicAdd(&b.h1[e_], cnt);
-            atomicAdd(&b.h1[STS_NBIN + e_], hi);
-            atomicAdd(&b.h1[2 * STS_NBIN + e_], lo & ((1ull << 44) - 1));
-        }
+        const int e = hot_lo + (int)threadIdx.x;
+        if (e >= 0 && e < STS_NBIN) flush_one(b, e, hi, lo);
     }
 }
 
@@ -618,19 +635,19 @@ __device__ __forceinline__ void flush_window(u64 *s_wacc, u64 &ma, u64 &mw)
 // tile's candidates above it are counted: when this step's cut exponent turns
 // out the same, the extraction pass has nothing left to do.
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG) k_tile_hist(const GateArg *__restrict__ gp, PassBufs b)
+__global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
     __shared__ TileSmem<AT> s;
-    __shared__ u64 s_hi[TT_COPIES * TT_NB]; // sum of mantissa >> 26
-    __shared__ u64 s_lo[TT_COPIES * TT_NB]; // sum of mantissa & (2^26-1), plus count << 44
+    __shared__ u64 s_hi[TT_SLOTS]; // sum of mantissa >> 26
+    __shared__ u64 s_lo[TT_SLOTS]; // sum of mantissa & (2^26-1), plus count << 44
     __shared__ u64 s_bw[STS_WG / 64], s_bk[STS_WG / 64];
     // window sums of the workgroup: candidates above the window, their part in
     // its exponent (mantissa sum >> 26, & (2^26-1)); candidates inside it, the
     // same two sums
     __shared__ u64 s_wacc[6];
     __shared__ u32 s_above, s_side;
-    for (int i = threadIdx.x; i < TT_COPIES * TT_NB; i += STS_WG) {
+    for (int i = threadIdx.x; i < TT_SLOTS; i += STS_WG) {
         s_hi[i] = 0;
         s_lo[i] = 0;
     }
@@ -670,7 +687,11 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(const GateArg *__restrict_
         ctl->side_ntiles = ntiles;
         ctl->side_slab_shift = 11 + M;
     }
-    const int copy = (int)(threadIdx.x % TT_COPIES);
+    const int copy = (int)(threadIdx.x % TT_HCOPIES);
+    // the hot exponents: the window's and the ones below it (most candidates
+    // fall below the cut), else around the previous cut
+    const int e_ref = predict ? e_w : (ctl->e_pred >= 0 ? ctl->e_pred : TT_EBASE + 116);
+    const int hot_lo = e_ref - (TT_HOT - 4);
     u64 bw = 0, bk = ~0ull;
     int since_flush = 0;
     for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -678,7 +699,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(const GateArg *__restrict_
             // a tile adds at most 2048 * 8 candidates to a bin, so after 8 tiles
             // the low sums stay below 2^43 and the counts below 2^17: flush
             __syncthreads();
-            flush_bins(b, s_hi, s_lo);
+            flush_bins(b, s_hi, s_lo, hot_lo);
             if (predict) flush_window(s_wacc, ma, mw);
             since_flush = 0;
         }
@@ -722,9 +743,12 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(const GateArg *__restrict_
                     ma += (ab && hw < wE1) ? mant : 0ull;
                 }
                 const int bin = e_ - TT_EBASE;
-                if (bin >= 0 && bin < TT_NB) {
-                    atomicAdd(&s_hi[bin * TT_COPIES + copy], mant >> 26);
-                    atomicAdd(&s_lo[bin * TT_COPIES + copy], (mant & ((1ull << 26) - 1)) | (1ull << 44));
+                const int hd = e_ - hot_lo;
+                if ((unsigned)hd < (unsigned)TT_HOT || (unsigned)bin < (unsigned)TT_NB) {
+                    const int f2 = (int)((wb >> 50) & (TT_HSUB - 1));
+                    const int slot = (unsigned)hd < (unsigned)TT_HOT ? TT_NB + (hd * TT_HSUB + f2) * TT_HCOPIES + copy : bin;
+                    atomicAdd(&s_hi[slot], mant >> 26);
+                    atomicAdd(&s_lo[slot], (mant & ((1ull << 26) - 1)) | (1ull << 44));
                 } else { // far outside the usual range: straight to the global bins
                     atomicAdd(&b.h1[e_], 1ull);
                     atomicAdd(&b.h1[STS_NBIN + e_], mant >> 26);
@@ -776,7 +800,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_hist(const GateArg *__restrict_
         s_bw[threadIdx.x >> 6] = bw;
         s_bk[threadIdx.x >> 6] = bk;
     }
-    flush_bins(b, s_hi, s_lo);
+    flush_bins(b, s_hi, s_lo, hot_lo);
     if (predict) {
         // this workgroup's window sums in its own slots (the pick adds the
         // workgroups up: no global atomics)
