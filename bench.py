@@ -296,11 +296,18 @@ def bench_batch(args):
     t = time.perf_counter()
     choice, timings = B.autotune(items, "c64")
     t_tune = time.perf_counter() - t
-    log(f"autotune {t_tune:.1f}s: " + ", ".join(f"s{k[0]}/g{k[1]} {v:.2f}s" for k, v in sorted(timings.items())))
-    res, t_batch = B.run_batch(items, "c64", choice[0], choice[1], packed=packed)
+    def tag(k):
+        return f"s{k[0]}/g{k[1]}/sort{k[3]}@2^{k[2]}"
+
+    log(f"autotune {t_tune:.1f}s: " + ", ".join(f"{tag(k)} {v:.2f}s" for k, v in sorted(timings.items())))
+    sort = (choice[2], choice[3])
+    res, t_batch = B.run_batch(items, "c64", choice[0], choice[1], packed=packed, sort=sort)
     same = all(all(a[f] == b[f] for f in ("peak_key", "peak_prob", "n_terms", "term_updates", "log10_cum_kept"))
                for a, b in zip(plain, res))
-    log(f"batch s{choice[0]}/g{choice[1]}: {t_batch:.2f}s, {upd / t_batch:.3e} updates/s, "
+    # captured-step replay against eager launches, each at its best stream count
+    eager = min((v for k, v in timings.items() if k[1] == 0), default=None)
+    replay = min((v for k, v in timings.items() if k[1] > 0), default=None)
+    log(f"batch {tag(choice)}: {t_batch:.2f}s, {upd / t_batch:.3e} updates/s, "
         f"{t_plain / t_batch:.2f}x the plain loop; results identical: {same}")
     if not same:
         raise SystemExit("batched results differ from the plain loop")
@@ -318,12 +325,14 @@ def bench_batch(args):
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"batch{len(items)}_uneven_n16-40_K2^12-2^20_c64", "circuits": len(items),
-                   "streams": choice[0], "graph_steps": choice[1]},
+                   "streams": choice[0], "graph_steps": choice[1],
+                   "sort_small_log2": choice[2], "sort_shape": choice[3]},
         "plain_loop": {"value": upd / t_plain, "seconds": t_plain},
         "batch_seconds": t_batch,
         "speedup_vs_plain": t_plain / t_batch,
         "autotune": {"seconds": t_tune, "sample": "every 4th circuit",
-                     "timings": {f"s{k[0]}/g{k[1]}": v for k, v in sorted(timings.items())}},
+                     "timings": {tag(k): v for k, v in sorted(timings.items())},
+                     "sample_seconds_eager_best": eager, "sample_seconds_replay_best": replay},
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -161,6 +161,24 @@ sts_status sts_stats(sts_ctx *ctx, double *W, double *kept_fraction, double *log
  * pointer may be NULL. Synchronises. */
 sts_status sts_counters(sts_ctx *ctx, uint64_t *gate_steps, uint64_t *term_updates, uint64_t *candidates);
 
+/* Shapes of the grouping sort (digit bits x keys per workgroup tile). The
+ * default, 8-bit digits in 4096-key tiles, suits large states: a digit's run
+ * in a tile averages 16 keys, so the scatter's writes coalesce. Small states
+ * sort in a chain of short launches, where 11-bit digits (fewer passes) or
+ * 2048-key tiles (more workgroups) can pay. */
+typedef enum {
+    STS_SORT_8x16 = 0,  /* 8-bit digits, 4096-key tiles (default)  */
+    STS_SORT_8x8 = 1,   /* 8-bit digits, 2048-key tiles            */
+    STS_SORT_11x16 = 2, /* 11-bit digits, 4096-key tiles           */
+    STS_SORT_11x8 = 3   /* 11-bit digits, 2048-key tiles           */
+} sts_sort_shape;
+
+/* From now on, sort states of at most 2^small_log2 terms with `shape` and
+ * larger ones with STS_SORT_8x16 (small_log2 = 0: always the default). The
+ * results do not depend on the shape. STS_E_ARG for small_log2 outside
+ * 0..40 or an unknown shape; call between steps (no gate pending). */
+sts_status sts_set_sort_shape(sts_ctx *ctx, int small_log2, int shape);
+
 /* Kernel kinds timed by sts_profile (the kernels of a gate step). */
 typedef enum {
     STS_K_RADIX_HIST = 0,   /* per-tile digit counts of a grouping-sort pass */
@@ -232,6 +250,8 @@ typedef struct {
                      /* once per state of the circuit's context (term buffer,  */
                      /* size bound, gate size) and replayed for later gates    */
                      /* with only the gate changed                             */
+    int sort_small_log2; /* each circuit's context: sts_set_sort_shape(         */
+    int sort_shape;      /* sort_small_log2, sort_shape); 0, 0 = the default    */
 } sts_batch_config;
 
 typedef struct {

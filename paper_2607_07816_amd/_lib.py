@@ -25,8 +25,9 @@ EXPORTS = (
     "sts_num_terms", "sts_read_terms", "sts_load_terms", "sts_stats", "sts_counters",
     "sts_profile", "sts_kernel_time", "sts_free", "sts_strerror", "sts_batch_run",
     "sts_server_create", "sts_server_submit", "sts_server_wait", "sts_server_stats", "sts_server_destroy",
-    "sts_step_static",
+    "sts_step_static", "sts_set_sort_shape",
 )
+SORT_SHAPES = {"8x16": 0, "8x8": 1, "11x16": 2, "11x8": 3}  # sts_sort_shape
 STATIC_MAX_TERMS = 65536  # STS_STATIC_MAX_TERMS
 
 KERNEL_KINDS = ("radix_hist", "radix_scan", "radix_pass", "group_hist", "pick1", "group_extract",
@@ -43,7 +44,8 @@ class Circuit(ctypes.Structure):
 
 class BatchConfig(ctypes.Structure):
     """sts_batch_config."""
-    _fields_ = [("precision", ctypes.c_int), ("n_streams", ctypes.c_int), ("graph_steps", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("n_streams", ctypes.c_int), ("graph_steps", ctypes.c_int),
+                ("sort_small_log2", ctypes.c_int), ("sort_shape", ctypes.c_int)]
 
 
 class CircuitResult(ctypes.Structure):
@@ -108,6 +110,7 @@ def load() -> ctypes.CDLL:
     L.sts_server_stats.argtypes = [vp] + [ctypes.POINTER(u64)] * 4
     L.sts_server_destroy.argtypes = [vp]
     L.sts_server_destroy.restype = None
+    L.sts_set_sort_shape.argtypes = [vp, i32, i32]
     L.sts_step_static.argtypes = [i32, u64, dbl, i32, vp, i32, vp, vp, vp, vp, u64, vp, vp, vp, vp]
     L.sts_strerror.argtypes = [i32]
     L.sts_strerror.restype = ctypes.c_char_p
@@ -230,6 +233,12 @@ class State:
         if k.shape != a.shape:
             raise ValueError("keys and amps differ in length")
         _check(load().sts_load_terms(self._ctx, k.shape[0], k.ctypes.data, a.ctypes.data), "sts_load_terms")
+
+    def set_sort_shape(self, small_log2: int, shape="8x16"):
+        """Sort states of at most 2^small_log2 terms with `shape` ("8x16",
+        "8x8", "11x16", "11x8": digit bits x keys per thread); 0 = default."""
+        code = SORT_SHAPES[shape] if isinstance(shape, str) else int(shape)
+        _check(load().sts_set_sort_shape(self._ctx, int(small_log2), code), "sts_set_sort_shape")
 
     def stats(self) -> dict:
         W, f, lc = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)

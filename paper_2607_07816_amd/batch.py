@@ -3,8 +3,10 @@ autotuner for the batch runner's launch configuration.
 
 A batch item is (circuit, K, p). Every circuit runs through its own context,
 exactly as it would alone; the batch only decides how many run at once
-(`streams`) and whether truncated gate steps are captured into HIP graphs
-and replayed with the next gate (`graph_steps` > 0).
+(`streams`), whether truncated gate steps are captured into HIP graphs
+and replayed with the next gate (`graph_steps` > 0), and which shape the
+grouping sort takes for small states (digit width and tile, `sort`). None of
+these changes a result.
 """
 from __future__ import annotations
 
@@ -57,16 +59,19 @@ def pack(items: Sequence[Tuple[object, int, float]], want_terms: bool = False) -
 
 
 def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, packed=None,
-              want_terms: bool = False) -> Tuple[list, float]:
+              want_terms: bool = False, sort: Tuple[int, str] = (0, "8x16")) -> Tuple[list, float]:
     """Run every (circuit, K, p) of `items`; returns (per-circuit result
     dicts in input order, wall seconds of the whole batch). With want_terms
-    each result also holds the final 'keys' and 'amps' (ascending keys)."""
+    each result also holds the final 'keys' and 'amps' (ascending keys).
+    sort = (small_log2, shape): states of at most 2^small_log2 terms are
+    grouped with that sort shape (sts_set_sort_shape)."""
     L = _lib.load()
     packed = packed if packed is not None else pack(items, want_terms)
     n = len(packed)
     arr = (_lib.Circuit * max(n, 1))(*[pk.c for pk in packed])
     res = (_lib.CircuitResult * max(n, 1))()
-    cfg = _lib.BatchConfig(_lib._prec(precision), int(streams), int(graph_steps))
+    shape = _lib.SORT_SHAPES[sort[1]] if isinstance(sort[1], str) else int(sort[1])
+    cfg = _lib.BatchConfig(_lib._prec(precision), int(streams), int(graph_steps), int(sort[0]), shape)
     t0 = time.perf_counter()
     rc = L.sts_batch_run(n, arr, ctypes.byref(cfg), res)
     dt = time.perf_counter() - t0
@@ -84,6 +89,9 @@ def run_batch(items, precision="c64", streams: int = 8, graph_steps: int = 0, pa
 
 
 DEFAULT_CANDIDATES = tuple((s, g) for s in (4, 8, 16, 32, 48) for g in (0, 16))
+# grouping-sort policies tried at the best (streams, graph) setting: states of
+# at most 2^small_log2 terms sorted with the shape (sts_set_sort_shape)
+DEFAULT_SORTS = ((0, "8x16"), (20, "11x16"), (20, "8x8"), (20, "11x8"))
 
 
 def batch_signature(items, precision="c64") -> str:
@@ -109,18 +117,21 @@ def _load_cache(path):
 
 def autotune(items, precision="c64", sample: Optional[Sequence[int]] = None,
              candidates: Iterable[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 1,
-             cache: Optional[str] = None):
-    """Time each (streams, graph_steps) candidate on a sample of the batch
-    and return (best config, {config: seconds}). The sample keeps the batch's
-    mix: by default every fourth circuit.
+             cache: Optional[str] = None, sorts: Iterable[Tuple[int, str]] = DEFAULT_SORTS):
+    """Time each (streams, graph_steps) candidate on a sample of the batch,
+    then each grouping-sort policy (small_log2, shape) at the best of them,
+    and return (best config (streams, graph_steps, small_log2, shape),
+    {config: seconds}). The sample keeps the batch's mix: by default every
+    fourth circuit. The sort policy chooses the sort's digit width and tile
+    by the state's size (log2 of its term bound).
 
     With `cache` (a JSON file path), a batch whose signature (batch_signature)
-    and candidate list were tuned before returns the stored choice and
-    timings without running anything; a new result is added to the file.
-    The kernels' own shapes (tile sizes, items per thread, digit width) are
-    fixed at build time and are not tuned here."""
+    and candidate lists were tuned before returns the stored choice and
+    timings without running anything; a new result is added to the file."""
     candidates = [tuple(int(x) for x in c) for c in candidates]
-    key = batch_signature(items, precision) + ":" + ",".join(f"{s}/{g}" for s, g in candidates)
+    sorts = [(int(a), str(b)) for a, b in sorts]
+    key = (batch_signature(items, precision) + ":" + ",".join(f"{s}/{g}" for s, g in candidates) + ":" +
+           ",".join(f"{a}/{b}" for a, b in sorts))
     if cache:
         hit = _load_cache(cache).get(key)
         if hit:
@@ -129,13 +140,21 @@ def autotune(items, precision="c64", sample: Optional[Sequence[int]] = None,
     idx = list(sample) if sample is not None else list(range(0, len(items), 4))
     sub = [items[i] for i in idx]
     packed = pack(sub)
-    timings = {}
-    for cfg in candidates:
+
+    def timed(streams, graph, sort):
         best = None
         for _ in range(repeats):
-            _, dt = run_batch(sub, precision, cfg[0], cfg[1], packed=packed)
+            _, dt = run_batch(sub, precision, streams, graph, packed=packed, sort=sort)
             best = dt if best is None else min(best, dt)
-        timings[cfg] = best
+        return best
+
+    timings = {}
+    default_sort = sorts[0] if sorts else (0, "8x16")
+    for s_, g_ in candidates:
+        timings[(s_, g_) + default_sort] = timed(s_, g_, default_sort)
+    best = min(timings, key=timings.get)
+    for sort in sorts[1:]:
+        timings[best[:2] + sort] = timed(best[0], best[1], sort)
     choice = min(timings, key=timings.get)
     if cache:
         data = _load_cache(cache)

@@ -52,7 +52,7 @@ Layout make_layout(u64 cap, int prec)
     const u64 asz = prec == STS_C128 ? 16 : 8;
     const u64 scap = side_capacity(cap);
     const u64 ttiles = tiled_tiles(cap);
-    const u64 tiles = ceil_div(cap, STS_TILE);
+    const u64 tiles = ceil_div(cap, 2048) + 1; // the smallest grouping-sort tile
     const u64 gtiles = ceil_div(cap, STS_GTILE);
     Layout L;
     u64 o = 0;
@@ -72,9 +72,9 @@ Layout make_layout(u64 cap, int prec)
     L.h1 = take(3 * STS_NBIN * 8);
     L.h2 = take(3 * STS_NBIN * 8);
     L.best = take(2 * STS_MAX_GROUPS * 8);
-    L.rcount = take(256 * tiles * 4);
-    L.rprefix = take(256 * tiles * 8);
-    L.rtotal = take(256 * 8);
+    L.rcount = take(2048 * tiles * 4); // per digit (up to 11-bit digits) and tile
+    L.rprefix = take(2048 * tiles * 8);
+    L.rtotal = take(2048 * 8);
     L.look_comp = take(gtiles * 8);
     L.t_above = take(ttiles * 4);
     L.t_side = take(ttiles * 4);
@@ -130,6 +130,8 @@ struct sts_ctx {
     u64 *keys[3] = {nullptr, nullptr, nullptr};
     void *amps[3] = {nullptr, nullptr, nullptr};
     int cur = 0;            // buffer with the state, or the sorted input of the pending gate
+    int radix_small_log2 = 0;               // states of at most 2^this terms are sorted with
+    int radix_small_shape = STS_RADIX_8x16; // this shape; larger ones with 8x16
     bool pending = false;   // a gate whose new amplitudes are not written yet
     GateArg gate;
     u64 n_bound = 1;        // upper bound on the terms in buffer cur
@@ -360,14 +362,21 @@ sts_status refuse_step(sts_ctx *c)
     return STS_E_CAPACITY;
 }
 
-// 8-bit digit passes of the grouping sort: enough bucket bits for the
-// state's size bound
+// the grouping sort's shape for the state's size bound (the context's
+// policy), and its digit passes: enough bucket bits for that bound
+int sort_shape(const sts_ctx *c)
+{
+    return c->radix_small_log2 > 0 && c->n_bound <= (1ull << c->radix_small_log2) ? c->radix_small_shape
+                                                                                  : STS_RADIX_8x16;
+}
+
 int sort_passes(const sts_ctx *c)
 {
     const u64 nb = std::max<u64>(c->n_bound, 2);
     int lg = 0;
     while ((1ull << lg) < nb && lg < 63) ++lg;
-    return std::min(std::max((lg + 7) / 8, 1), STS_MAX_PASSES);
+    const int bits = sts_radix_bits(sort_shape(c));
+    return std::min(std::max((lg + bits - 1) / bits, 1), 32 / bits);
 }
 
 // group the state in buffer cur by the hash bucket of key & notmask (the
@@ -376,20 +385,21 @@ int sort_passes(const sts_ctx *c)
 sts_status sort_state(sts_ctx *c, const u64 *notmask, int *sorted, int *hb_out)
 {
     const u64 nb = std::max<u64>(c->n_bound, 2);
+    const int shape = sort_shape(c);
+    const int bits = sts_radix_bits(shape);
     const int npass = sort_passes(c);
-    const int hb = 8 * npass;
-    const int tiles = (int)std::max<u64>(ceil_div(nb, STS_TILE), 1);
+    const int hb = bits * npass;
+    const int tiles = (int)std::max<u64>(ceil_div(nb, sts_radix_tile(shape)), 1);
     const int a = (c->cur + 1) % 3, b = (c->cur + 2) % 3;
     int src = c->cur, dst = a;
     for (int p = 0; p < npass; ++p) {
-        const int shift = 64 - hb + 8 * p;
-        STS_LAUNCH(c, STS_K_RADIX_HIST, launch_radix_count(c->keys[src], &c->ctl->cnt[src], notmask, shift, c->rcount,
-                                                            c->tiles_cap, tiles, c->stream));
-        STS_LAUNCH(c, STS_K_RADIX_SCAN, launch_radix_scan(c->rcount, c->rprefix, c->rtotal, &c->ctl->cnt[src],
-                                                           c->tiles_cap, c->stream));
-        STS_LAUNCH(c, STS_K_RADIX_PASS, launch_radix_pass(c->prec, c->keys[src], c->amps[src], c->keys[dst], c->amps[dst],
-                                     &c->ctl->cnt[src], &c->ctl->cnt[dst], notmask, shift, c->rprefix, c->rtotal,
-                                     c->tiles_cap, tiles, c->stream));
+        const int shift = 64 - hb + bits * p;
+        for (int what = 0; what < 3; ++what) {
+            const int kind = what == 0 ? STS_K_RADIX_HIST : (what == 1 ? STS_K_RADIX_SCAN : STS_K_RADIX_PASS);
+            STS_LAUNCH(c, kind, launch_radix(what, shape, c->prec, c->keys[src], c->amps[src], c->keys[dst],
+                                             c->amps[dst], &c->ctl->cnt[src], &c->ctl->cnt[dst], notmask, shift,
+                                             c->rcount, c->rprefix, c->rtotal, c->tiles_cap, tiles, c->stream));
+        }
         src = dst;
         dst = dst == a ? b : a;
     }
@@ -560,7 +570,7 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     c->stream = (hipStream_t)hip_stream;
     c->cap = cap;
     c->scap = side_capacity(cap);
-    c->tiles_cap = ceil_div(cap, STS_TILE);
+    c->tiles_cap = ceil_div(cap, 2048) + 1;
     c->gtiles_cap = ceil_div(cap, STS_GTILE);
     const Layout L = make_layout(cap, precision);
     if (arena) {
@@ -629,7 +639,7 @@ sts_status sts_apply_gate(sts_ctx *c, int m, const int *qubits, const double *U)
         g.uptr = c->dU;
     }
     int sorted = c->cur, hb = 8;
-    g.hb = 8 * sort_passes(c); // the bucket bits the sort below uses
+    g.hb = sts_radix_bits(sort_shape(c)) * sort_passes(c); // the bucket bits the sort below uses
     STS_TRY(c, launch_set_gate(g, c->dgate, c->stream));
     c->gate_dev = c->dgate;
     st = sort_state(c, &c->dgate->notmask, &sorted, &hb);
@@ -715,6 +725,20 @@ sts_status sts_truncate(sts_ctx *c)
     c->cur = out;
     c->n_bound = nb;
     c->pending = false;
+    return STS_OK;
+}
+
+sts_status sts_set_sort_shape(sts_ctx *c, int small_log2, int shape)
+{
+    static_assert(STS_SORT_8x16 == STS_RADIX_8x16 && STS_SORT_8x8 == STS_RADIX_8x8 &&
+                      STS_SORT_11x16 == STS_RADIX_11x16 && STS_SORT_11x8 == STS_RADIX_11x8,
+                  "public and internal sort shapes agree");
+    sts_status st = check_live(c);
+    if (st != STS_OK) return st;
+    if (small_log2 < 0 || small_log2 > 40 || shape < 0 || shape >= STS_RADIX_SHAPES) return STS_E_ARG;
+    if (c->pending) return STS_E_STATE; // the pending gate's sort already ran with the old shape
+    c->radix_small_log2 = small_log2;
+    c->radix_small_shape = shape;
     return STS_OK;
 }
 
@@ -896,7 +920,7 @@ sts_status sts_step_static(int n_qubits, uint64_t max_terms, double mass, int pr
     c.stream = (hipStream_t)hip_stream;
     c.cap = STS_STATIC_MAX_TERMS;
     c.scap = side_capacity(c.cap);
-    c.tiles_cap = ceil_div(c.cap, STS_TILE);
+    c.tiles_cap = ceil_div(c.cap, 2048) + 1;
     c.gtiles_cap = ceil_div(c.cap, STS_GTILE);
     c.mem = (unsigned char *)base;
     bind_layout(&c, L);
@@ -1058,7 +1082,7 @@ sts_status step_replayed(sts_ctx *c, StepGraphs *gs, int m, const int *qubits, c
     // replay with the new gate: the same bucket bits (same size bound)
     GateArg g;
     fill_gate(&g, m, qubits, U);
-    g.hb = 8 * sort_passes(c);
+    g.hb = sts_radix_bits(sort_shape(c)) * sort_passes(c);
     GateArg *dst = c->dgate;
     void *args[2] = {&g, &dst};
     hipKernelNodeParams p{};

@@ -30,13 +30,14 @@ struct BatchJob {
 };
 
 // one circuit start to finish on an existing stream and arena
-void run_one(const sts_circuit &c, int prec, int graph_steps, hipStream_t s, void *arena, size_t arena_bytes,
-             sts_circuit_result *r)
+void run_one(const sts_circuit &c, int prec, int graph_steps, int sort_small_log2, int sort_shape, hipStream_t s,
+             void *arena, size_t arena_bytes, sts_circuit_result *r)
 {
     const auto t0 = std::chrono::steady_clock::now();
     std::memset(r, 0, sizeof(*r));
     sts_ctx *ctx = nullptr;
     sts_status st = sts_init(&ctx, c.n_qubits, c.max_terms, c.mass, prec, s, arena, arena_bytes, circuit_cap(c));
+    if (st == STS_OK) st = sts_set_sort_shape(ctx, sort_small_log2, sort_shape);
     StepGraphs *gs = graph_steps > 0 && st == STS_OK ? step_graphs_new() : nullptr;
     u64 qo = 0, uo = 0;
     u64 i = 0;
@@ -69,6 +70,8 @@ extern "C" sts_status sts_batch_run(int n, const sts_circuit *circuits, const st
     if (n < 0 || (n > 0 && (!circuits || !results)) || !cfg) return STS_E_ARG;
     if (cfg->precision != STS_C128 && cfg->precision != STS_C64) return STS_E_ARG;
     if (cfg->n_streams < 1 || cfg->n_streams > 64 || cfg->graph_steps < 0) return STS_E_ARG;
+    if (cfg->sort_small_log2 < 0 || cfg->sort_small_log2 > 40 || cfg->sort_shape < 0 || cfg->sort_shape > 3)
+        return STS_E_ARG;
     for (int i = 0; i < n; ++i)
         if (!circuit_valid(circuits[i])) return STS_E_ARG;
     if (n == 0) return STS_OK;
@@ -113,7 +116,8 @@ extern "C" sts_status sts_batch_run(int n, const sts_circuit *circuits, const st
         }
         for (int j = next.fetch_add(1); j < n; j = next.fetch_add(1)) {
             const int idx = jobs[j].idx;
-            run_one(circuits[idx], cfg->precision, cfg->graph_steps, s, arena, bytes, &results[idx]);
+            run_one(circuits[idx], cfg->precision, cfg->graph_steps, cfg->sort_small_log2, cfg->sort_shape, s, arena,
+                    bytes, &results[idx]);
         }
         (void)hipStreamSynchronize(s);
         (void)hipFree(arena);

@@ -63,13 +63,20 @@ struct PassBufs {
 };
 
 // launch helpers (return hipError_t of the launch)
-hipError_t launch_radix_count(const u64 *keys, const u64 *n_in, const u64 *notmask, int shift, u32 *counts,
-                              u64 tiles_cap, int tiles, hipStream_t s);
-hipError_t launch_radix_scan(const u32 *counts, u64 *prefix, u64 *totals, const u64 *n_in, u64 tiles_cap,
-                             hipStream_t s);
-hipError_t launch_radix_pass(int prec, const u64 *kin, const void *ain, u64 *kout, void *aout, const u64 *n_in,
-                             u64 *n_out, const u64 *notmask, int shift, const u64 *prefix, const u64 *totals,
-                             u64 tiles_cap, int tiles, hipStream_t s);
+// grouping-sort shapes (digit bits x keys per thread): 8x16 is the default
+#define STS_RADIX_8x16 0   // 8-bit digits, 4096-key tiles
+#define STS_RADIX_8x8 1    // 8-bit digits, 2048-key tiles
+#define STS_RADIX_11x16 2  // 11-bit digits, 4096-key tiles
+#define STS_RADIX_11x8 3   // 11-bit digits, 2048-key tiles
+#define STS_RADIX_SHAPES 4
+inline int sts_radix_bits(int shape) { return shape >= STS_RADIX_11x16 ? 11 : 8; }
+inline u64 sts_radix_tile(int shape) { return (shape & 1) ? 2048ull : 4096ull; }
+
+// one step of a grouping-sort pass: what = 0 digit counts per tile, 1 their
+// scan (one workgroup per digit), 2 the scatter
+hipError_t launch_radix(int what, int shape, int prec, const u64 *kin, const void *ain, u64 *kout, void *aout,
+                        const u64 *n_in, u64 *n_out, const u64 *notmask, int shift, u32 *counts, u64 *prefix,
+                        u64 *totals, u64 tiles_cap, int tiles, hipStream_t s);
 
 hipError_t launch_group_hist(int prec, const GateArg &g, const PassBufs &b, int grid, bool tiled, hipStream_t s);
 int group_hist_capacity(int prec, int m, bool tiled); // resident workgroups of the histogram pass

@@ -111,3 +111,16 @@ def test_replayed_steps_equal_eager_at_every_checkpoint(prec):
         assert np.array_equal(r["keys"], k), c.name
         assert np.array_equal(r["amps"].view(np.uint64), a.view(np.uint64)), c.name
     say(f"[batch] replayed prefixes {lengths} equal the eager runs ({prec})")
+
+
+@pytest.mark.parametrize("sort", [(20, "11x16"), (20, "8x8"), (12, "11x8")])
+def test_batch_sort_shapes_equal_alone(sort):
+    # the sort shape the autotuner may choose for small states changes no
+    # circuit's result
+    items = small_items(8, seed=14)
+    res, _ = B.run_batch(items, "c128", 4, 1, sort=sort)
+    for (c, K, p), r in zip(items, res):
+        ref = alone(c, K, p, "c128")
+        assert r["status"] == 0
+        for f in FIELDS:
+            assert r[f] == ref[f], (c.name, sort, f)

@@ -396,3 +396,33 @@ def test_four_qubit_gate_tiled_and_untiled(S, prec, cap_factor):
     else:
         assert np.array_equal(kg, ko)
         assert np.abs(ag - ao).max() <= 1e-5
+
+
+@pytest.mark.parametrize("shape", ["8x8", "11x16", "11x8"])
+@pytest.mark.parametrize("n,N,m,K,p", [
+    (40, 19 * 4096 + 1234, 2, 30000, 0.95),   # several tiles of either size, a ragged tail
+    (24, 3000, 2, 1000, 0.0),                 # one pass of 11-bit digits (2^11 < N <= 2^22 takes two)
+    (48, 300001, 1, 0, 0.9),                  # 11-bit: two passes; 8-bit: three
+    (30, 5000, 3, 7000, 0.0),
+])
+def test_sort_shapes_fp64(S, shape, n, N, m, K, p):
+    # the grouping sort's shape (digit bits x tile) changes the order the
+    # gate passes see, never the result: bit for bit the oracle's
+    rng = np.random.default_rng(n * 7 + N + m)
+    keys, amps = random_state(rng, n, N)
+    qs = tuple(int(q) for q in rng.choice(n, size=m, replace=False))
+    U = C.haar_unitary(rng, 1 << m)
+    say(f"sort shape {shape} n={n} N={N} m={m} K={K} p={p}")
+    cap = max((len(keys) << m) + 16, 1024, K)
+    with S.State(n, K=K, p=p, precision="c128", capacity=cap) as st:
+        st.set_sort_shape(40, shape)
+        st.load_terms(keys, amps)
+        st.apply_gate(qs, U)
+        st.truncate()
+        kg, ag = st.read_terms()
+        stats = st.stats()
+    ko, ao, info = oracle_step(keys, amps, qs, U, K, p)
+    assert_same_fp64(kg, ag, ko, ao)
+    assert np.array_equal(ag.view(np.uint64), ao.view(np.uint64))
+    if info is not None:
+        assert stats["kept_fraction"] == info["fraction"]
