@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=256, help="circuits of the c4 workload")
     ap.add_argument("--fuse", type=int, default=0, metavar="M",
                     help="reorder and fuse the circuit into blocks of up to M qubits first (Sec. VI.A); 0 = off")
+    ap.add_argument("--sort", default="8x16", choices=["8x16", "8x8", "11x16", "11x8"],
+                    help="grouping-sort shape of the 48q/24q workloads: digit bits x keys per thread")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="terms in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -145,6 +147,8 @@ def main():
     # 4-qubit blocks take the tiled passes when the state holds at most half
     # of the capacity
     st = State(circuit.n, K=K, p=p, precision=prec, capacity=2 * K if args.fuse >= 4 else K)
+    if args.sort != "8x16":
+        st.set_sort_shape(40, args.sort)
     gi = 0
 
     def run(nsteps):
@@ -247,6 +251,7 @@ def main():
         "config": {
             "workload": circuit.name + f"_K2^{K.bit_length() - 1}_p{p}_{prec}",
             "fused_max_m": args.fuse,
+            "sort_shape": args.sort,
             "n_qubits": circuit.n,
             "K": K,
             "p": p,

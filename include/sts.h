@@ -341,7 +341,7 @@ void sts_server_destroy(sts_server *s);
  * not overlap the inputs; n_out points to one u64 in device memory; stats,
  * if not NULL, to two doubles in device memory that receive W and the kept
  * fraction (as sts_stats). Terms come out in no particular order.
- * Every working buffer lives in one static device array of 16 MiB per
+ * Every working buffer lives in one static device array of 32 MiB per
  * device (held until the process ends), laid out for at most
  * STS_STATIC_MAX_TERMS terms: n_in or K above that is STS_E_CAPACITY, with
  * nothing launched. The call only enqueues work on hip_stream (NULL = the

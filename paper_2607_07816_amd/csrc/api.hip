@@ -38,7 +38,7 @@ u64 align_up(u64 x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
-    u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
+    u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, side_amp, sub_key, sub_w, h1, h2, best, rcount, rprefix, rtotal, look_comp,
         t_above, t_side, t_off, tctr, dU, sub_cnt, wpart, sbins, gate, total;
 };
 
@@ -67,6 +67,7 @@ Layout make_layout(u64 cap, int prec)
     for (int i = 0; i < 3; ++i) L.amps[i] = take(cap * asz);
     L.side_key = take(scap * 8);
     L.side_w = take(scap * 8);
+    L.side_amp = take(scap * asz);
     L.sub_key = take((u64)STS_SUB_CAP * 8);
     L.sub_w = take((u64)STS_SUB_CAP * 8);
     L.h1 = take(3 * STS_NBIN * 8);
@@ -76,8 +77,8 @@ Layout make_layout(u64 cap, int prec)
     L.rprefix = take(2048 * tiles * 8);
     L.rtotal = take(2048 * 8);
     L.look_comp = take(gtiles * 8);
-    L.t_above = take(ttiles * 4);
-    L.t_side = take(ttiles * 4);
+    L.t_above = take(ttiles * 4 * 4); // up to 4 slabs per tile
+    L.t_side = take(ttiles * 4 * 4);
     L.t_off = take(ttiles * 8);
     L.tctr = take(16 * 4);
     L.dU = take(kULen * 8);
@@ -91,7 +92,7 @@ Layout make_layout(u64 cap, int prec)
 
 // the working memory of sts_step_static: one array per device, holding a
 // context laid out for STS_STATIC_MAX_TERMS terms of either precision
-constexpr size_t kStaticBytes = 16ull << 20;
+constexpr size_t kStaticBytes = 32ull << 20;
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
 
 // its address on the current device (the array's name is a host-side
@@ -139,6 +140,7 @@ struct sts_ctx {
     DevCtl *ctl_save = nullptr; // the control block as it was before a step that may be refused
     u64 *h1 = nullptr, *h2 = nullptr, *best = nullptr;
     u64 *side_key = nullptr, *side_w = nullptr, *sub_key = nullptr, *sub_w = nullptr;
+    void *side_amp = nullptr;
     u32 *rcount = nullptr;                          // per-tile digit counts of a scatter pass
     u64 *rprefix = nullptr, *rtotal = nullptr, *look_comp = nullptr;
     u32 *t_above = nullptr, *t_side = nullptr;
@@ -256,6 +258,7 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     b.best = c->best;
     b.side_key = c->side_key;
     b.side_w = c->side_w;
+    b.side_amp = c->side_amp;
     b.side_cap = c->scap;
     b.sub_key = c->sub_key;
     b.sub_w = c->sub_w;
@@ -308,6 +311,7 @@ void bind_layout(sts_ctx *c, const Layout &L)
     }
     c->side_key = (u64 *)(c->mem + L.side_key);
     c->side_w = (u64 *)(c->mem + L.side_w);
+    c->side_amp = (void *)(c->mem + L.side_amp);
     c->sub_key = (u64 *)(c->mem + L.sub_key);
     c->sub_w = (u64 *)(c->mem + L.sub_w);
     c->h1 = (u64 *)(c->mem + L.h1);
@@ -682,6 +686,9 @@ sts_status sts_truncate(sts_ctx *c)
     if (tiled && c->gate.m >= 1 && c->gate.m <= 3 && c->n_bound >= STS_SAMPLE_MIN)
         STS_LAUNCH(c, STS_K_SAMPLE, launch_group_sample(c->prec, c->gate, b, c->stream));
     b.predict = tiled ? 1 : 0; // the histogram pass also extracts the predicted window
+    // and keeps the candidates above it, so that a step whose cut falls in
+    // the window writes its survivors without running the gate again
+    b.copy = tiled ? 1 : 0;
     STS_LAUNCH(c, STS_K_GROUP_HIST, launch_group_hist(c->prec, c->gate, b, G, tiled, c->stream));
     b.predict = 0;
     STS_LAUNCH(c, STS_K_PICK1, launch_pick1(b, G, 0, tiled ? 1 : 0, c->stream));

@@ -38,9 +38,10 @@ struct DevCtl {
     u64 tot_updates;     // input terms of those truncations
     u64 tot_cand;        // candidates of those truncations
     u64 side_n;          // candidates copied to the side buffer (dense layout)
-    u64 side_ntiles;     // tiled layout: tiles, each owning a slab of 2^side_slab_shift entries
+    u64 side_ntiles;     // tiled layout: slabs of 2^side_slab_shift entries
     int side_slab_shift;
     int side_dense;      // 1: entries [0, side_n) (look-back pass); 0: per-tile slabs
+    int side_spt_log2;   // tiled layout: each tile owns 2^side_spt_log2 consecutive slabs
     // fields updated with atomics sit on cache lines of their own: every
     // workgroup of every kernel reads the fields around them, and reads of a
     // line wait behind the atomics queued on it

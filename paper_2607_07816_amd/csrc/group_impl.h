@@ -646,7 +646,6 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
     // its exponent (mantissa sum >> 26, & (2^26-1)); candidates inside it, the
     // same two sums
     __shared__ u64 s_wacc[6];
-    __shared__ u32 s_above, s_side;
     for (int i = threadIdx.x; i < TT_SLOTS; i += STS_WG) {
         s_hi[i] = 0;
         s_lo[i] = 0;
@@ -682,11 +681,16 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
     // mantissas of < 2^53: no overflow), then added to the workgroup's sums
     // in LDS split at bit 26; their counts come from the per-tile totals
     u64 ma = 0, mw = 0;
+    // each wave of a tile owns one slab of 512 << M entries (room for all its
+    // candidates): the window's from its start, those above the window from
+    // its end, claimed with counters the wave keeps itself
     if (predict && blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->side_dense = 0;
-        ctl->side_ntiles = ntiles;
-        ctl->side_slab_shift = 11 + M;
+        ctl->side_ntiles = ntiles << 2;
+        ctl->side_slab_shift = 9 + M;
+        ctl->side_spt_log2 = 2;
     }
+    const int wv = (int)(threadIdx.x >> 6);
     const int copy = (int)(threadIdx.x % TT_HCOPIES);
     // the hot exponents: the window's and the ones below it (most candidates
     // fall below the cut), else around the previous cut
@@ -708,82 +712,79 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
         const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
         const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
         __syncthreads(); // previous tile done with the LDS
-        if (threadIdx.x == 0) {
-            s_above = 0;
-            s_side = 0;
-        }
         stage_tile<AT, M>(s, g, keys, amps, lo, hi);
         __syncthreads();
-        const u64 slab = tile << (11 + M);
-        u32 above = 0;
+        const u64 slab = ((tile << 2) + (u64)wv) << (9 + M);
+        const u64 slab_end = slab + (512ull << M);
+        const bool keep_above = predict && b.copy && slab_end <= b.side_cap;
+        u32 c_in = 0, c_ab = 0; // the wave's claims so far (the same in every lane)
 #pragma unroll 1
         for (int k = 0; k < TT_IT; ++k) {
             const u64 e = base + (u64)k * STS_WG + threadIdx.x;
             Group<AT, M> G;
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
-            u64 wbs[1 << M];
-            u32 sidebits = 0;
 #pragma unroll Unroll<M>::value
             for (int i = 0; i < (1 << M); ++i) {
                 const AT o = group_out<AT, M>(g, G, i);
                 const bool cand = G.present && (M == 0 || nonzero(o));
                 const u64 wb = weight_bits(o);
-                wbs[i] = wb;
                 const int e_ = (int)(wb >> 52);
-                const u64 key = G.rest | deposit_bits<M>((u32)i, g);
-                if (!cand) continue;
-                const u64 mant = sts_mant(wb);
+                bool ab = false, inw = false;
+                if (cand) {
+                    const u64 mant = sts_mant(wb);
+                    if (predict) {
+                        const u32 hw = (u32)(wb >> 32);
+                        ab = hw >= wH;
+                        inw = hw >= wL && !ab;
+                        mw += inw ? mant : 0ull;
+                        ma += (ab && hw < wE1) ? mant : 0ull;
+                    }
+                    const int bin = e_ - TT_EBASE;
+                    const int hd = e_ - hot_lo;
+                    if ((unsigned)hd < (unsigned)TT_HOT || (unsigned)bin < (unsigned)TT_NB) {
+                        const int f2 = (int)((wb >> 50) & (TT_HSUB - 1));
+                        const int slot = (unsigned)hd < (unsigned)TT_HOT ? TT_NB + (hd * TT_HSUB + f2) * TT_HCOPIES + copy : bin;
+                        atomicAdd(&s_hi[slot], mant >> 26);
+                        atomicAdd(&s_lo[slot], (mant & ((1ull << 26) - 1)) | (1ull << 44));
+                    } else { // far outside the usual range: straight to the global bins
+                        atomicAdd(&b.h1[e_], 1ull);
+                        atomicAdd(&b.h1[STS_NBIN + e_], mant >> 26);
+                        atomicAdd(&b.h1[2 * STS_NBIN + e_], mant & ((1ull << 26) - 1));
+                    }
+                    if (M == 0) { // the peak is only asked of the state itself (sts_peak)
+                        const u64 key = G.rest;
+                        const u64 tagged = wb | (1ull << 63);
+                        if (tagged > bw || (tagged == bw && key < bk)) {
+                            bw = tagged;
+                            bk = key;
+                        }
+                    }
+                }
                 if (predict) {
-                    const u32 hw = (u32)(wb >> 32);
-                    const bool ab = hw >= wH;
-                    const bool inw = hw >= wL && !ab;
-                    above += ab ? 1u : 0u;
-                    sidebits |= inw ? (1u << i) : 0u;
-                    mw += inw ? mant : 0ull;
-                    ma += (ab && hw < wE1) ? mant : 0ull;
-                }
-                const int bin = e_ - TT_EBASE;
-                const int hd = e_ - hot_lo;
-                if ((unsigned)hd < (unsigned)TT_HOT || (unsigned)bin < (unsigned)TT_NB) {
-                    const int f2 = (int)((wb >> 50) & (TT_HSUB - 1));
-                    const int slot = (unsigned)hd < (unsigned)TT_HOT ? TT_NB + (hd * TT_HSUB + f2) * TT_HCOPIES + copy : bin;
-                    atomicAdd(&s_hi[slot], mant >> 26);
-                    atomicAdd(&s_lo[slot], (mant & ((1ull << 26) - 1)) | (1ull << 44));
-                } else { // far outside the usual range: straight to the global bins
-                    atomicAdd(&b.h1[e_], 1ull);
-                    atomicAdd(&b.h1[STS_NBIN + e_], mant >> 26);
-                    atomicAdd(&b.h1[2 * STS_NBIN + e_], mant & ((1ull << 26) - 1));
-                }
-                if (M == 0) { // the peak is only asked of the state itself (sts_peak)
-                    const u64 tagged = wb | (1ull << 63);
-                    if (tagged > bw || (tagged == bw && key < bk)) {
-                        bw = tagged;
-                        bk = key;
+                    const u64 m_ab = __ballot(ab), m_in = __ballot(inw);
+                    if (inw) {
+                        const u64 at = slab + c_in + (u64)__popcll(m_in & sts_lanemask_lt());
+                        if (at < b.side_cap) {
+                            b.side_key[at] = G.rest | deposit_bits<M>((u32)i, g);
+                            b.side_w[at] = wb;
+                            if (keep_above) ((AT *)b.side_amp)[at] = o;
+                        }
+                    } else if (ab && keep_above) {
+                        const u64 at = slab_end - 1 - (c_ab + (u64)__popcll(m_ab & sts_lanemask_lt()));
+                        b.side_key[at] = G.rest | deposit_bits<M>((u32)i, g);
+                        ((AT *)b.side_amp)[at] = o;
                     }
-                }
-            }
-            if (predict) {
-                u32 at = wave_claim_n<M + 1>((u32)__popc(sidebits), &s_side);
-#pragma unroll Unroll<M>::value
-                for (int i = 0; i < (1 << M); ++i) {
-                    if (!((sidebits >> i) & 1u)) continue;
-                    if (slab + at < b.side_cap) {
-                        b.side_key[slab + at] = G.rest | deposit_bits<M>((u32)i, g);
-                        b.side_w[slab + at] = wbs[i];
-                    }
-                    ++at;
+                    c_in += (u32)__popcll(m_in);
+                    c_ab += (u32)__popcll(m_ab);
                 }
             }
         }
-        if (predict) {
-            atomicAdd(&s_above, above);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                b.t_above[tile] = s_above;
-                b.t_side[tile] = s_side;
-                s_wacc[0] += s_above;
-                s_wacc[3] += s_side;
-            }
+        if (predict && sts_lane() == 0) {
+            const u64 sl = (tile << 2) + (u64)wv;
+            b.t_above[sl] = c_ab;
+            b.t_side[sl] = c_in;
+            atomicAdd((unsigned long long *)&s_wacc[0], (unsigned long long)c_ab);
+            atomicAdd((unsigned long long *)&s_wacc[3], (unsigned long long)c_in);
         }
     }
 #pragma unroll
@@ -1024,6 +1025,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restri
         ctl->side_dense = 0;
         ctl->side_ntiles = ntiles;
         ctl->side_slab_shift = 11 + M;
+        ctl->side_spt_log2 = 0;
     }
     if (tile >= ntiles) return;
     const bool all = b.materialise || ctl->keep_all;
@@ -1077,11 +1079,77 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restri
     }
 }
 
+// a survivor's amplitude as written: scaled by 1/sqrt(kept mass) when the
+// cut dropped anything
+template <typename AT> __device__ __forceinline__ AT out_amp(AT o, bool rescale, double scale)
+{
+    typedef typename Scalar<AT>::T R;
+    if (rescale) {
+        o.x = (R)((double)o.x * scale);
+        o.y = (R)((double)o.y * scale);
+    }
+    return o;
+}
+
+// The survivors of a tile whose cut fell in the histogram pass's window:
+// every candidate above the window (kept at the ends of the tile's slabs)
+// and those of the window ranked at or above the threshold term (at their
+// starts), copied rather than computed again. Same set and values as the
+// computing path of k_tile_emit.
+template <typename AT>
+__device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int spl, int shift, u64 out0, u64 thr_w,
+                                              u64 thr_k, bool rescale, double scale, u32 *s_out)
+{
+    constexpr int UN = 4;
+    const TileSlabs ab = tile_slabs(b.t_above, tile, spl, shift, true, b.side_cap);
+    const TileSlabs sd = tile_slabs(b.t_side, tile, spl, shift, false, b.side_cap);
+    const u32 na = ab.n, ns = sd.n;
+    const AT *sa = (const AT *)b.side_amp;
+    AT *oa = (AT *)b.out_amps;
+    for (u32 j0 = 0; j0 < na; j0 += UN * STS_WG) {
+        u64 kk[UN];
+        AT aa[UN];
+#pragma unroll
+        for (int r = 0; r < UN; ++r) {
+            const u32 j = j0 + (u32)r * STS_WG + threadIdx.x;
+            if (j < na) {
+                const u64 i = slab_at(ab, j);
+                kk[r] = b.side_key[i];
+                aa[r] = sa[i];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < UN; ++r) {
+            const u32 j = j0 + (u32)r * STS_WG + threadIdx.x;
+            if (j < na && out0 + j < b.out_cap) {
+                b.out_keys[out0 + j] = kk[r];
+                oa[out0 + j] = out_amp(aa[r], rescale, scale);
+            }
+        }
+    }
+    // the window's survivors after them, in claim order
+    for (u32 j0 = 0; j0 < ns; j0 += STS_WG) {
+        const u32 j = j0 + threadIdx.x;
+        bool keep = false;
+        u64 k = 0, i = 0;
+        if (j < ns) {
+            i = slab_at(sd, j);
+            const u64 w = b.side_w[i];
+            k = b.side_key[i];
+            keep = w > thr_w || (w == thr_w && k <= thr_k);
+        }
+        const u64 at = out0 + na + wave_claim(keep, s_out);
+        if (keep && at < b.out_cap) {
+            b.out_keys[at] = k;
+            oa[at] = out_amp(sa[i], rescale, scale);
+        }
+    }
+}
+
 template <typename AT, int M>
 __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
-    typedef typename Scalar<AT>::T R;
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_out;
     const int tid = threadIdx.x;
@@ -1089,14 +1157,22 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
     const u64 tile = blockIdx.x; // below the tile arrays' length (the launch's bound)
     // every control load issued before any is used
     const u64 n = *b.n_in;
-    const int keep_all = ctl->keep_all, dropped = ctl->dropped;
+    const int keep_all = ctl->keep_all, dropped = ctl->dropped, hit = ctl->pred_hit;
     const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
     const double scale = ctl->scale;
+    const int shift = ctl->side_slab_shift, spl = ctl->side_spt_log2;
     const u64 out0 = b.t_off[tile];
     const u64 ntiles = (n + TT_TG - 1) / TT_TG;
     if (tile >= ntiles) return;
     const bool all = b.materialise || keep_all;
     const bool rescale = !all && dropped;
+    // the histogram pass kept this tile's survivors when its slabs fit
+    if (b.copy && !all && hit && spl == 2 && shift == 9 + M && ((tile + 1) << (11 + M)) <= b.side_cap) {
+        if (tid == 0) s_out = 0;
+        __syncthreads();
+        tile_copy_out<AT>(b, tile, spl, shift, out0, thr_w, thr_k, rescale, scale, &s_out);
+        return;
+    }
     const u64 *keys = b.keys;
     const AT *amps = (const AT *)b.amps;
     const u64 base = tile * TT_TG;
@@ -1127,13 +1203,8 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
         for (int i = 0; i < (1 << M); ++i) {
             if (!((keepbits >> i) & 1u)) continue;
             if (out0 + at < b.out_cap) {
-                AT o = os[i];
-                if (rescale) {
-                    o.x = (R)((double)o.x * scale);
-                    o.y = (R)((double)o.y * scale);
-                }
                 b.out_keys[out0 + at] = G.rest | deposit_bits<M>((u32)i, g);
-                ((AT *)b.out_amps)[out0 + at] = o;
+                ((AT *)b.out_amps)[out0 + at] = out_amp(os[i], rescale, scale);
             }
             ++at;
         }

@@ -38,6 +38,7 @@ struct PassBufs {
     // compaction targets
     u64 *side_key;        // side buffer: candidates of the exponent holding the cut
     u64 *side_w;
+    void *side_amp;       // their amplitudes (histogram pass with `copy`)
     u64 side_cap;
     u64 *sub_key;         // the level-2 subset of the side buffer, in STS_SUB_REGIONS
     u64 *sub_w;           // regions of sub_cap / STS_SUB_REGIONS entries
@@ -47,20 +48,77 @@ struct PassBufs {
     u64 *out_keys;        // new state
     void *out_amps;
     u64 out_cap;
-    u32 *t_above;         // per tile: survivors certain before the cut (tiled passes)
-    u32 *t_side;          // per tile: side-buffer entries in the tile's slab
+    u32 *t_above;         // per slab: survivors certain before the cut (tiled passes)
+    u32 *t_side;          // per slab: side-buffer entries in it
     u64 *t_off;           // per tile: output offset of its survivors
     u64 *look;            // look-back words, one per tile
     u32 *tile_ctr;
     u32 epoch;            // tags look-back words of this launch
     int materialise;      // 1: keep every candidate, no rescale (no truncation)
     int predict;          // histogram pass: also extract the window of the predicted cut
+    int copy;             // histogram pass: also keep every candidate above the window, with
+                          // the window's amplitudes, in the tile's slab; emit pass: when the
+                          // window held the cut, copy the survivors out of the slabs
     u64 *wpart;           // [6][STS_MAX_GROUPS]: per histogram workgroup, the count of candidates
                           // above the window and the mantissa sums (>> 26, & (2^26-1)) of those in
                           // the window's exponent; then the count and sums of those inside it
     u64 *sbins;           // sampling pass: STS_SW_BANKS x STS_SW_NB counts (u32), as many masses
                           // (float), then 4 totals per bank
 };
+
+// The slabs of one tile in the tiled side-buffer layout: 2^spl (1 or 4)
+// consecutive slabs of 2^shift entries, slab s holding cnt[s] entries of one
+// kind, at its start (window entries) or at its end (entries above the
+// window). A tile's entries of that kind are visited through one flat index.
+// (Scalar fields rather than arrays, so that the struct stays in registers.)
+struct TileSlabs {
+    u64 f0, f1, f2, f3; // first entry of each slab's run
+    u32 p1, p2, p3, n;  // ends of the first three runs in the flat index; entries in all
+};
+
+__device__ __forceinline__ TileSlabs tile_slabs(const u32 *cnt, u64 tile, int spl, int shift, bool at_end, u64 cap)
+{
+    u64 f[4];
+    u32 c[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        c[w] = 0;
+        f[w] = 0;
+        if (w < (1 << spl)) {
+            const u64 sl = (tile << spl) + (u64)w;
+            const u64 base = sl << shift, end = base + (1ull << shift);
+            u32 k = cnt[sl];
+            if (at_end) {
+                if (end > cap) k = 0;
+                f[w] = end - k;
+            } else {
+                if (base >= cap) k = 0;
+                else if ((u64)k > cap - base) k = (u32)(cap - base);
+                f[w] = base;
+            }
+            c[w] = k;
+        }
+    }
+    TileSlabs t;
+    t.f0 = f[0];
+    t.f1 = f[1];
+    t.f2 = f[2];
+    t.f3 = f[3];
+    t.p1 = c[0];
+    t.p2 = t.p1 + c[1];
+    t.p3 = t.p2 + c[2];
+    t.n = t.p3 + c[3];
+    return t;
+}
+
+// physical index of a tile's j-th entry (j < n)
+__device__ __forceinline__ u64 slab_at(const TileSlabs &t, u32 j)
+{
+    if (j < t.p1) return t.f0 + j;
+    if (j < t.p2) return t.f1 + (j - t.p1);
+    if (j < t.p3) return t.f2 + (j - t.p2);
+    return t.f3 + (j - t.p3);
+}
 
 // launch helpers (return hipError_t of the launch)
 // grouping-sort shapes (digit bits x keys per thread): 8x16 is the default

@@ -362,8 +362,9 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     for (int i = t; i < 3 * STS_NBIN; i += 256) h1[i] = 0;
 }
 
-// The side buffer is either dense (entries [0, side_n)) or split into one
-// slab of 2^shift entries per tile, slab t holding t_side[t] entries. Its
+// The side buffer is either dense (entries [0, side_n)) or split into slabs
+// of 2^shift entries (one per tile, or one per wave of a tile in the
+// histogram pass), slab s holding t_side[s] entries from its start. Its
 // entries are visited through a flat index f over the whole layout.
 struct SideView {
     const u64 *key;
@@ -392,13 +393,14 @@ __device__ __forceinline__ bool side_valid(const SideView &v, u64 f)
     return v.dense || (f & ((1ull << v.shift) - 1)) < (u64)v.cnt[f >> v.shift];
 }
 
-// The same entries as a list of chunks: the slabs of the tiled layout, or
-// runs of 8192 entries of the dense one. Workgroups walk chunks; threads walk
-// the entries of a chunk.
+// The same entries as a list of chunks: the tiles of the tiled layout (each
+// the runs of its 1 or 4 slabs), or runs of 8192 entries of the dense one.
+// Workgroups walk chunks; threads walk the entries of a chunk.
 struct SideChunks {
     u64 nchunks;
     int dense;
     int shift;
+    int spl;
     u64 n;          // dense: entries
     u64 cap;
     const u32 *cnt;
@@ -409,26 +411,29 @@ __device__ __forceinline__ SideChunks side_chunks(const PassBufs &b, const DevCt
     SideChunks c;
     c.dense = ctl->side_dense;
     c.shift = ctl->side_slab_shift;
+    c.spl = ctl->side_spt_log2;
     c.cap = b.side_cap;
     c.cnt = b.t_side;
     c.n = ctl->side_n < b.side_cap ? ctl->side_n : b.side_cap;
-    c.nchunks = c.dense ? (c.n + 8191) / 8192 : ctl->side_ntiles;
+    c.nchunks = c.dense ? (c.n + 8191) / 8192 : (ctl->side_ntiles >> c.spl);
     return c;
 }
 
-// first entry and entry count of chunk t
-__device__ __forceinline__ void chunk_range(const SideChunks &c, u64 t, u64 &base, u64 &count)
+// the entries of chunk t (visited with slab_at)
+__device__ __forceinline__ TileSlabs chunk_of(const SideChunks &c, u64 t)
 {
-    if (c.dense) {
-        base = t * 8192;
-        count = c.n - base < 8192 ? c.n - base : 8192;
-    } else {
-        base = t << c.shift;
-        count = c.cnt[t];
-        if (base >= c.cap) count = 0;
-        else if (count > c.cap - base) count = c.cap - base;
-    }
+    if (!c.dense) return tile_slabs(c.cnt, t, c.spl, c.shift, false, c.cap);
+    TileSlabs s;
+    const u64 base = t * 8192;
+    const u32 count = (u32)(c.n - base < 8192 ? c.n - base : 8192);
+    s.f0 = base;
+    s.f1 = s.f2 = s.f3 = 0;
+    s.p1 = s.p2 = s.p3 = s.n = count;
+    return s;
 }
+
+// most entries a chunk can hold
+__device__ __forceinline__ u64 chunk_max(const SideChunks &c) { return c.dense ? 8192ull : (1ull << (c.shift + c.spl)); }
 
 // within-exponent rank key: ascending V = descending weight, then ascending key
 __device__ __forceinline__ u128 rank_key(u64 wbits, u64 key)
@@ -608,26 +613,26 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
     // loads in flight; a round of four chunks adds at most 4 * chunk_max
     // entries, and the bins are flushed before they could overflow
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const u64 chunk_max = sc.dense ? 8192 : (1ull << sc.shift);
+    const u64 cmax = chunk_max(sc);
     u64 since = 0;
     for (u64 r0 = (u64)blockIdx.x * 4; r0 < sc.nchunks; r0 += (u64)gridDim.x * 4) {
-        if (since + 4 * chunk_max > SH_FLUSH) { // uniform across the workgroup
+        if (since + 4 * cmax > SH_FLUSH) { // uniform across the workgroup
             __syncthreads();
             side_flush(h2, s_hi, s_lo);
             __syncthreads();
             since = 0;
         }
-        since += 4 * chunk_max;
+        since += 4 * cmax;
         const u64 t = r0 + wv;
         if (t >= sc.nchunks) continue;
-        u64 base, count;
-        chunk_range(sc, t, base, count);
-        for (u64 i0 = 0; i0 < count; i0 += UN * 64) {
+        const TileSlabs ch = chunk_of(sc, t);
+        const u32 count = ch.n;
+        for (u32 i0 = 0; i0 < count; i0 += UN * 64) {
             u64 w[UN];
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
-                const u64 i = i0 + (u64)r * 64 + lane;
-                w[r] = i < count ? b.side_w[base + i] : ~0ull;
+                const u32 i = i0 + (u32)r * 64 + lane;
+                w[r] = i < count ? b.side_w[slab_at(ch, i)] : ~0ull;
             }
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
@@ -689,18 +694,19 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
     u32 *cnt = &b.sub_cnt[region * 32];
     const u64 lt = sts_lanemask_lt();
     for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
-        u64 cbase, count;
-        chunk_range(sc, t, cbase, count);
-        for (u64 i0 = 0; i0 < count; i0 += UN * 256) {
+        const TileSlabs ch = chunk_of(sc, t);
+        const u32 count = ch.n;
+        for (u32 i0 = 0; i0 < count; i0 += UN * 256) {
             u64 w[UN];
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
-                const u64 i = i0 + (u64)r * 256 + threadIdx.x;
-                w[r] = i < count ? b.side_w[cbase + i] : ~0ull;
+                const u32 j = i0 + (u32)r * 256 + threadIdx.x;
+                w[r] = j < count ? b.side_w[slab_at(ch, j)] : ~0ull;
             }
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
-                const u64 i = cbase + i0 + (u64)r * 256 + threadIdx.x;
+                const u32 j = i0 + (u32)r * 256 + threadIdx.x;
+                const u64 i = j < count ? slab_at(ch, j) : 0ull;
                 bool take = false;
                 u64 k = 0;
                 if (w[r] != ~0ull) {
@@ -936,32 +942,38 @@ __global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
     // every control load issued before any is used
     const u64 n = *b.n_in;
     const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
-    const int shift = ctl->side_slab_shift;
-    u64 ns = b.t_side[tile];
+    const int shift = ctl->side_slab_shift, spl = ctl->side_spt_log2;
     const u64 ntiles = (n + 2047) / 2048;
     if (tile >= ntiles) return;
-    const u64 base = tile << shift;
-    if (base >= b.side_cap) ns = 0;
-    else if (ns > b.side_cap - base) ns = b.side_cap - base;
+    // the tile's window entries (one slab, or one per wave of the histogram
+    // pass), and its candidates certain before the cut
+    const TileSlabs sd = tile_slabs(b.t_side, tile, spl, shift, false, b.side_cap);
+    u64 na = 0;
+    for (int w = 0; w < (1 << spl); ++w) na += b.t_above[(tile << spl) + (u64)w];
+    const u32 ns = sd.n;
     u32 c = 0;
-    for (u64 i0 = 0; i0 < ns; i0 += UN * 256) {
-        u64 w[UN];
+    for (u32 i0 = 0; i0 < ns; i0 += UN * 256) {
+        u64 w[UN], k[UN];
 #pragma unroll
         for (int r = 0; r < UN; ++r) {
-            const u64 i = i0 + (u64)r * 256 + threadIdx.x;
-            w[r] = i < ns ? b.side_w[base + i] : 0;
+            const u32 j = i0 + (u32)r * 256 + threadIdx.x;
+            if (j < ns) {
+                const u64 i = slab_at(sd, j);
+                w[r] = b.side_w[i];
+                k[r] = b.side_key[i];
+            }
         }
 #pragma unroll
         for (int r = 0; r < UN; ++r) {
-            const u64 i = i0 + (u64)r * 256 + threadIdx.x;
-            if (i >= ns) continue;
+            const u32 j = i0 + (u32)r * 256 + threadIdx.x;
+            if (j >= ns) continue;
             // ranked at or above the threshold term; the key decides only a tie
-            c += (w[r] > thr_w || (w[r] == thr_w && b.side_key[base + i] <= thr_k)) ? 1u : 0u;
+            c += (w[r] > thr_w || (w[r] == thr_w && k[r] <= thr_k)) ? 1u : 0u;
         }
     }
     u32 tot;
     (void)block_excl_scan<u32, 256>(c, s_scratch, &tot);
-    if (threadIdx.x == 0) b.t_off[tile] = (u64)b.t_above[tile] + tot;
+    if (threadIdx.x == 0) b.t_off[tile] = na + tot;
 }
 
 __global__ void __launch_bounds__(1024) k_tile_scan(PassBufs b)
