@@ -409,10 +409,18 @@ constexpr int TT_LD = TT_TG + 2 * TT_H;
 constexpr int TT_EBASE = 1023 - 127 + 8; // exponent fields [904, 1032) live in LDS bins
 constexpr int TT_NB = 128;
 
+// bkt holds the low 16 bits of each key's hash bucket: neighbouring runs in
+// the sorted order have neighbouring buckets, which differ there, so a run of
+// equal low bits is the run of equal buckets (the key test decides the group)
 template <typename AT> struct TileSmem {
     u64 key[TT_LD];
-    u32 bkt[TT_LD];
+    unsigned short bkt[TT_LD];
 };
+
+__device__ __forceinline__ u32 tile_bucket(u64 key, u64 notmask, int sh)
+{
+    return (u32)(sts_mix64(key & notmask) >> sh) & 0xffffu;
+}
 
 // stage the keys of global terms [lo, hi) and their hash buckets into LDS:
 // every load of the thread is issued before any of them is used, so the tile
@@ -438,7 +446,7 @@ __device__ __forceinline__ void stage_tile(TileSmem<AT> &s, const GateArg &g, co
         const int li = r * STS_WG + (int)threadIdx.x;
         if (li < cnt) {
             s.key[li] = kk[r];
-            if (M > 0) s.bkt[li] = (u32)(sts_mix64(kk[r] & g.notmask) >> sh);
+            if (M > 0) s.bkt[li] = (unsigned short)tile_bucket(kk[r], g.notmask, sh);
         }
     }
 }
@@ -506,7 +514,7 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     if (p < 0 && lo > 0) { // the run goes on below the staged range
         for (u64 q = lo; q > 0; --q) {
             const u64 kq = keys[q - 1];
-            if ((u32)(sts_mix64(kq & nm) >> sh) != b) break;
+            if (tile_bucket(kq, nm, sh) != b) break;
             if ((kq & nm) == rest) return;
         }
     }
@@ -530,7 +538,7 @@ __device__ __forceinline__ void tile_group(const TileSmem<AT> &s, const GateArg 
     if (f == last) { // the run goes on above the staged range
         for (u64 q = hi; q < n; ++q) {
             const u64 kq = keys[q];
-            if ((u32)(sts_mix64(kq & nm) >> sh) != b) break;
+            if (tile_bucket(kq, nm, sh) != b) break;
             if ((kq & nm) == rest) group_set<AT, M>(G, extract_bits<M>(kq, g), amps[q]);
         }
     }
@@ -629,6 +637,30 @@ __device__ __forceinline__ void flush_window(u64 *s_wacc, u64 &ma, u64 &mw)
     ma = mw = 0;
 }
 
+// Level-2 bins of a sampled window: the top 11 fraction bits of the rank
+// key inside the window's exponent (as the side-buffer histogram bins them).
+// A window spans three sub-bins of 1/32 octave, i.e. at most 192 of them.
+constexpr int TT_W2 = 192;
+constexpr int TT_W2_LOW = 20; // split of the mantissa sums, as in the side pass
+
+// add a workgroup's level-2 window bins to the device copy and clear them
+__device__ __forceinline__ void flush_w2(const PassBufs &b, u64 *s_w2hi, u64 *s_w2lo, u32 d_lo)
+{
+    for (int i = threadIdx.x; i < TT_W2; i += STS_WG) {
+        const u64 lo = s_w2lo[i];
+        const u64 c = lo >> 44;
+        if (c) {
+            const u128 tot = ((u128)s_w2hi[i] << TT_W2_LOW) + (u128)(lo & ((1ull << 44) - 1));
+            const u32 d = d_lo + (u32)i;
+            atomicAdd(&b.h2w[d], c);
+            atomicAdd(&b.h2w[STS_NBIN + d], (u64)(tot >> 26));
+            atomicAdd(&b.h2w[2 * STS_NBIN + d], (u64)tot & ((1ull << 26) - 1));
+        }
+        s_w2hi[i] = 0;
+        s_w2lo[i] = 0;
+    }
+}
+
 // histogram pass over tiles (static tile assignment, persistent grid). With
 // b.predict, the candidates whose exponent field equals the previous step's
 // cut exponent (ctl->e_pred) also go to the tile's side-buffer slab, and the
@@ -646,9 +678,15 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
     // its exponent (mantissa sum >> 26, & (2^26-1)); candidates inside it, the
     // same two sums
     __shared__ u64 s_wacc[6];
+    // level-2 bins of a sampled window (sums split at bit 20, count << 44)
+    __shared__ u64 s_w2hi[TT_W2], s_w2lo[TT_W2];
     for (int i = threadIdx.x; i < TT_SLOTS; i += STS_WG) {
         s_hi[i] = 0;
         s_lo[i] = 0;
+    }
+    for (int i = threadIdx.x; i < TT_W2; i += STS_WG) {
+        s_w2hi[i] = 0;
+        s_w2lo[i] = 0;
     }
     if (threadIdx.x < 6) s_wacc[threadIdx.x] = 0;
     DevCtl *ctl = b.ctl;
@@ -660,11 +698,13 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
     // the sampling pass set for this step, else the previous cut's octave
     int e_w = -1;
     u64 w_lo = 0, w_hi = 0;
+    bool fine = false; // a sampled window: also bin its candidates for level 2
     if (b.predict) {
         if (ctl->w_mode) {
             e_w = ctl->e_w;
             w_lo = ctl->w_lo;
             w_hi = ctl->w_hi;
+            fine = true;
         } else if (ctl->e_pred >= 0) {
             e_w = ctl->e_pred;
             w_lo = (u64)e_w << 52;
@@ -672,6 +712,9 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
         }
     }
     const bool predict = e_w >= 0;
+    // first level-2 bin of the window (its heaviest weights)
+    const u32 d_lo = (u32)((((1ull << 52) - 1) - (w_hi & ((1ull << 52) - 1))) >> 41);
+    const u32 d_top = 2047u - d_lo;
     // The window's edges are multiples of 2^47 in the weight bits, so the
     // high words decide: inside when wL <= hi < wH, above when hi >= wH,
     // above but in the window's exponent when also hi < wE1.
@@ -705,6 +748,7 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
             __syncthreads();
             flush_bins(b, s_hi, s_lo, hot_lo);
             if (predict) flush_window(s_wacc, ma, mw);
+            if (fine) flush_w2(b, s_w2hi, s_w2lo, d_lo);
             since_flush = 0;
         }
         ++since_flush;
@@ -738,6 +782,16 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
                         inw = hw >= wL && !ab;
                         mw += inw ? mant : 0ull;
                         ma += (ab && hw < wE1) ? mant : 0ull;
+                        if (fine && inw) {
+                            // digit 2047 - (top 11 fraction bits), less the window's first
+                            const u32 rel = d_top - ((hw >> 9) & 2047u);
+                            if (rel < (u32)TT_W2) {
+                                atomicAdd(&s_w2hi[rel], mant >> TT_W2_LOW);
+                                atomicAdd(&s_w2lo[rel], (mant & ((1ull << TT_W2_LOW) - 1)) | (1ull << 44));
+                            } else { // outside the window's bins: cannot happen; fail the step
+                                atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+                            }
+                        }
                     }
                     const int bin = e_ - TT_EBASE;
                     const int hd = e_ - hot_lo;
@@ -802,6 +856,7 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
         s_bk[threadIdx.x >> 6] = bk;
     }
     flush_bins(b, s_hi, s_lo, hot_lo);
+    if (fine) flush_w2(b, s_w2hi, s_w2lo, d_lo);
     if (predict) {
         // this workgroup's window sums in its own slots (the pick adds the
         // workgroups up: no global atomics)

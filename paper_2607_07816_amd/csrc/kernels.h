@@ -34,6 +34,7 @@ struct PassBufs {
     DevCtl *ctl;
     // level-1 histogram (per exponent field) and per-workgroup best term
     u64 *h1;              // [3][STS_NBIN]: count, mantissa>>26, mantissa & (2^26-1)
+    u64 *h2w;             // the same for level 2 of a sampled window (histogram pass)
     u64 *best;            // [2][max groups]: (wbits | 2^63), key
     // compaction targets
     u64 *side_key;        // side buffer: candidates of the exponent holding the cut

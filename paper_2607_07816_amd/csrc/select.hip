@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     DevCtl *ctl = b.ctl;
     u64 *h1 = b.h1;
     // the exponent of the window the histogram pass copied (predicted steps)
-    const int e_w = predicted ? (ctl->w_mode ? ctl->e_w : ctl->e_pred) : -1;
+    const int w_mode = ctl->w_mode;
+    const int e_w = predicted ? (w_mode ? ctl->e_w : ctl->e_pred) : -1;
     if (t < 6) s_w[t] = 0;
 
     // own bins: every load issued before any is used
@@ -355,7 +356,10 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
                     ctl->R_hi = R_hi;
                 }
             }
-            if (lane == 0) ctl->w_mode = 0; // a window serves one step
+            if (lane == 0) {
+                ctl->w2_mode = predicted && w_mode; // the histogram pass binned the window for level 2
+                ctl->w_mode = 0;                     // a window serves one step
+            }
         }
     }
     __syncthreads();
@@ -592,17 +596,11 @@ __device__ __forceinline__ void side_flush(u64 *h2, u64 *s_hi, u64 *s_lo)
     }
 }
 
-__global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
+// this workgroup's share of the level-2 histogram of the side buffer, added
+// to h2
+__device__ __forceinline__ void side_bins(const PassBufs &b, DevCtl *ctl, u64 *h2, u64 *s_hi, u64 *s_lo)
 {
     constexpr int UN = 16; // entries in flight per lane
-    __shared__ u64 s_hi[STS_NBIN];
-    __shared__ u64 s_lo[STS_NBIN];
-    __shared__ u128 s_m[256];
-    __shared__ u64 s_c[256];
-    __shared__ u32 s_hit, s_flag;
-    __shared__ Sub s_sub;
-    DevCtl *ctl = b.ctl;
-    if (ctl->keep_all) return;
     for (int i = threadIdx.x; i < STS_NBIN; i += 256) {
         s_hi[i] = 0;
         s_lo[i] = 0;
@@ -647,27 +645,51 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
     }
     __syncthreads();
     side_flush(h2, s_hi, s_lo);
-    if (!sts_last_block(&ctl->done[1], &s_flag)) return;
-    if (threadIdx.x == 0) {
-        s_sub.cnt_before = ctl->cnt_before;
-        s_sub.mb = make128(ctl->mb_lo, ctl->mb_hi); // the window's exponent above it, or 0
-        s_sub.vpre = 0;
-        s_sub.vshift = 116;
-        s_sub.count = ctl->sub_count;
-    }
-    __syncthreads();
-    const u128 R = make128(ctl->R_lo, ctl->R_hi);
-    if (pick_digit<256>(h2, h2 + STS_NBIN, h2 + 2 * STS_NBIN, true, ctl->K, R, 11, &s_sub, s_m, s_c, &s_hit)) {
-        if (threadIdx.x == 0) {
-            sub_store(s_sub, ctl);
-            ctl->level = 2;
-            for (int i = 0; i <= STS_SUB_REGIONS; ++i) st_agent(&b.sub_cnt[i * 32], 0u);
-        }
-    } else if (threadIdx.x == 0) {
-        atomicOr(&ctl->flags, STS_F_UNRESOLVED);
-    }
-    for (int i = threadIdx.x; i < 3 * STS_NBIN; i += 256) st_agent(&h2[i], 0ull);
 }
+
+__global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
+{
+    __shared__ u64 s_hi[STS_NBIN];
+    __shared__ u64 s_lo[STS_NBIN];
+    __shared__ u128 s_m[256];
+    __shared__ u64 s_c[256];
+    __shared__ u32 s_hit, s_flag;
+    __shared__ Sub s_sub;
+    DevCtl *ctl = b.ctl;
+    const int keep_all = ctl->keep_all, w2 = ctl->w2_mode;
+    // the histogram pass binned a sampled window that holds the cut: its
+    // level-2 bins are complete, and only the pick is left
+    const bool fine = w2 && ctl->pred_hit && !keep_all;
+    if (keep_all && !w2) return;
+    if (!keep_all && !fine) side_bins(b, ctl, h2, s_hi, s_lo);
+    if (!sts_last_block(&ctl->done[1], &s_flag)) return;
+    if (!keep_all) {
+        const u64 *hs = fine ? b.h2w : h2;
+        if (threadIdx.x == 0) {
+            s_sub.cnt_before = ctl->cnt_before;
+            s_sub.mb = make128(ctl->mb_lo, ctl->mb_hi); // the window's exponent above it, or 0
+            s_sub.vpre = 0;
+            s_sub.vshift = 116;
+            s_sub.count = ctl->sub_count;
+        }
+        __syncthreads();
+        const u128 R = make128(ctl->R_lo, ctl->R_hi);
+        if (pick_digit<256>(hs, hs + STS_NBIN, hs + 2 * STS_NBIN, true, ctl->K, R, 11, &s_sub, s_m, s_c, &s_hit)) {
+            if (threadIdx.x == 0) {
+                sub_store(s_sub, ctl);
+                ctl->level = 2;
+                for (int i = 0; i <= STS_SUB_REGIONS; ++i) st_agent(&b.sub_cnt[i * 32], 0u);
+            }
+        } else if (threadIdx.x == 0) {
+            atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+        }
+        if (!fine)
+            for (int i = threadIdx.x; i < 3 * STS_NBIN; i += 256) st_agent(&h2[i], 0ull);
+    }
+    if (w2)
+        for (int i = threadIdx.x; i < 3 * STS_NBIN; i += 256) st_agent(&b.h2w[i], 0ull);
+}
+
 
 // ---------------------------------------------------------------------------
 // copy the level-2 subset out of the side buffer (many workgroups), so the
