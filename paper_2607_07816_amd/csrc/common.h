@@ -15,7 +15,8 @@ typedef unsigned __int128 u128;
 #define STS_WG 256            // threads per workgroup in the streaming kernels
 #define STS_NBIN 2048         // histogram bins per selection level
 #define STS_NL 20             // 64-bit limbs of the exact mass accumulator
-#define STS_SMALL 4096        // a subset this small is sorted in LDS
+#define STS_SMALL 4096        // a subset this small fits the final LDS sort
+#define STS_FINAL_SORT 512    // the final workgroup adds 11-bit levels until its subset is this small
 #define STS_MAXM 5            // largest gate (qubits)
 #define STS_MAX_PASSES 4      // radix passes per sort (8-bit digits)
 #define STS_TILE_ITEMS 16     // keys per thread in a radix tile

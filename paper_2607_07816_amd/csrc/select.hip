@@ -11,7 +11,7 @@
 //              rank key V = ((2^52 - 1 - fraction) << 64) | key, from the side
 //              buffer of that exponent's candidates,
 //   level 3+ - further 11-bit digits of V inside one workgroup, until at most
-//              4096 terms remain; those are sorted in LDS.
+//              512 terms remain; those are sorted in LDS.
 // Masses are exact: each bin carries the exact integer sum of its weights'
 // mantissas, levels >= 2 share one exponent, and level 1 prefixes are exact
 // integers on the 2^-1074 grid. Every decision therefore equals the one made
@@ -822,8 +822,10 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     if (t == 0) sub_load(s_sub, ctl);
     __syncthreads();
 
-    // further levels until the subset fits the LDS sort
-    while (s_sub.count > STS_SMALL && s_sub.vshift > 0) {
+    // further levels until the subset is small (a level is a pass over the
+    // subset and a block scan; the bitonic sort below costs a barrier per
+    // stage, so levels are the cheaper way down)
+    while (s_sub.count > STS_FINAL_SORT && s_sub.vshift > 0) {
         const int vshift = s_sub.vshift;
         const int dw = vshift < 11 ? vshift : 11;
         const u128 vpre = s_sub.vpre;
