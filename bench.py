@@ -46,11 +46,13 @@ def kernel_bytes(kind: str, amp_bytes: int, n_in: float, n_out: float, n_side: f
     if kind == "radix_hist":
         return 8 * n_in                 # keys only
     if kind == "group_hist":
-        return term * n_in              # read every term once (partners are neighbours)
+        # read every term once (partners are neighbours); keep the survivors
+        # above the cut's window in the side slabs (about all of them)
+        return term * n_in + term * n_out
     if kind == "group_extract":
         return term * n_in + 16 * n_side
     if kind == "group_emit":
-        return term * n_in + term * n_out
+        return 2 * term * n_out         # survivors copied out of the slabs
     if kind == "side_hist":
         return 8 * n_side
     if kind == "side_extract":

@@ -20,7 +20,8 @@ def test_kernel_bytes_model():
     assert b.kernel_bytes("radix_pass", 8, n, 0, 0) == 2 * 16 * n
     assert b.kernel_bytes("radix_pass", 16, n, 0, 0) == 2 * 24 * n
     assert b.kernel_bytes("radix_hist", 8, n, 0, 0) == 8 * n
-    assert b.kernel_bytes("group_emit", 8, n, n // 2, 0) == 16 * n + 16 * (n // 2)
+    assert b.kernel_bytes("group_emit", 8, n, n // 2, 0) == 2 * 16 * (n // 2)
+    assert b.kernel_bytes("group_hist", 16, n, n // 2, 0) == 24 * n + 24 * (n // 2)
     assert b.kernel_bytes("pick1", 8, n, n, n) == 0.0
 
 
