@@ -326,6 +326,19 @@ __device__ __forceinline__ int sts_lane() { return __lane_id(); }
 
 __device__ __forceinline__ u64 sts_lanemask_lt() { return (1ull << sts_lane()) - 1ull; }
 
+// set bits of the wave mask m below this lane (two mbcnt instructions)
+__device__ __forceinline__ u32 sts_lanes_below(u64 m)
+{
+    return __builtin_amdgcn_mbcnt_hi((u32)(m >> 32), __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
+}
+
+// store v at a byte offset below 4 GiB from a base that is the same in every
+// lane: the address stays a scalar base plus a 32-bit lane offset
+template <typename T> __device__ __forceinline__ void sts_store_at(T *base, u32 byte_off, const T &v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(base) + byte_off) = v;
+}
+
 // The workgroups of a launch are dealt to the XCDs in turn (workgroup b to
 // XCD b % 8), and each XCD has its own L2. sts_xcd_tile renumbers them so
 // that every XCD works through one contiguous range of tiles: neighbouring

@@ -733,7 +733,7 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
         ctl->side_slab_shift = 9 + M;
         ctl->side_spt_log2 = 2;
     }
-    const int wv = (int)(threadIdx.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); // uniform: kept in a scalar register
     const int copy = (int)(threadIdx.x % TT_HCOPIES);
     // the hot exponents: the window's and the ones below it (most candidates
     // fall below the cut), else around the previous cut
@@ -759,8 +759,12 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
         stage_tile<AT, M>(s, g, keys, amps, lo, hi);
         __syncthreads();
         const u64 slab = ((tile << 2) + (u64)wv) << (9 + M);
-        const u64 slab_end = slab + (512ull << M);
-        const bool keep_above = predict && b.copy && slab_end <= b.side_cap;
+        const bool slab_fits = slab + (512ull << M) <= b.side_cap;
+        const bool keep_above = predict && b.copy && slab_fits;
+        // the wave's slab: bases in scalar registers, 32-bit offsets per lane
+        u64 *const sk = b.side_key + slab;
+        u64 *const sw = b.side_w + slab;
+        AT *const sa = (AT *)b.side_amp + slab;
         u32 c_in = 0, c_ab = 0; // the wave's claims so far (the same in every lane)
 #pragma unroll 1
         for (int k = 0; k < TT_IT; ++k) {
@@ -817,16 +821,18 @@ __global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restri
                 if (predict) {
                     const u64 m_ab = __ballot(ab), m_in = __ballot(inw);
                     if (inw) {
-                        const u64 at = slab + c_in + (u64)__popcll(m_in & sts_lanemask_lt());
-                        if (at < b.side_cap) {
-                            b.side_key[at] = G.rest | deposit_bits<M>((u32)i, g);
-                            b.side_w[at] = wb;
-                            if (keep_above) ((AT *)b.side_amp)[at] = o;
+                        if (slab_fits) {
+                            const u32 at = c_in + sts_lanes_below(m_in);
+                            sts_store_at(sk, at * 8u, G.rest | deposit_bits<M>((u32)i, g));
+                            sts_store_at(sw, at * 8u, wb);
+                            if (keep_above) sts_store_at(sa, at * (u32)sizeof(AT), o);
+                        } else { // cannot happen (the side buffer holds every tile's slabs)
+                            atomicOr(&ctl->flags, STS_F_SIDE_OVERFLOW);
                         }
                     } else if (ab && keep_above) {
-                        const u64 at = slab_end - 1 - (c_ab + (u64)__popcll(m_ab & sts_lanemask_lt()));
-                        b.side_key[at] = G.rest | deposit_bits<M>((u32)i, g);
-                        ((AT *)b.side_amp)[at] = o;
+                        const u32 at = ((512u << M) - 1u) - c_ab - sts_lanes_below(m_ab);
+                        sts_store_at(sk, at * 8u, G.rest | deposit_bits<M>((u32)i, g));
+                        sts_store_at(sa, at * (u32)sizeof(AT), o);
                     }
                     c_in += (u32)__popcll(m_in);
                     c_ab += (u32)__popcll(m_ab);
