@@ -82,7 +82,7 @@ Layout make_layout(u64 cap, int prec)
     L.t_side = take(ttiles * 4 * 4);
     L.t_off = take(ttiles * 8);
     L.tctr = take(16 * 4);
-    L.dU = take(kULen * 8);
+    L.dU = take(kULen * 8 + kULen * 4); // U in FP64, then its FP32 rounding
     L.sub_cnt = take((STS_SUB_REGIONS + 1) * 128);
     L.wpart = take(6 * STS_MAX_GROUPS * 8);
     L.sbins = take(STS_SW_BANKS * (STS_SW_NB + 4) * 8);
@@ -595,7 +595,8 @@ sts_status sts_init(sts_ctx **out, int n_qubits, uint64_t max_terms, double mass
     bind_layout(c, L);
 
     hipError_t e = hipHostMalloc((void **)&c->hctl, sizeof(DevCtl), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->hU, kULen * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->hU, kULen * (sizeof(double) + sizeof(float)), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->u_event, hipEventDisableTiming);
     if (e != hipSuccess) {
         sts_free(c);
@@ -638,12 +639,18 @@ sts_status sts_apply_gate(sts_ctx *c, int m, const int *qubits, const double *U)
     if (m > 3) {
         // the previous copy from the staging buffer must have finished
         if (c->u_event_live) STS_TRY(c, hipEventSynchronize(c->u_event));
-        std::memcpy(c->hU, U, (size_t)2 * dim * dim * sizeof(double));
-        STS_TRY(c, hipMemcpyAsync(c->dU, c->hU, (size_t)2 * dim * dim * sizeof(double), hipMemcpyHostToDevice,
+        // the FP64 entries, then their FP32 roundings (nearest-even) right
+        // after them: one copy
+        const size_t nd = (size_t)2 * dim * dim;
+        std::memcpy(c->hU, U, nd * sizeof(double));
+        float *hf = reinterpret_cast<float *>(c->hU + nd);
+        for (size_t i = 0; i < nd; ++i) hf[i] = (float)U[i];
+        STS_TRY(c, hipMemcpyAsync(c->dU, c->hU, nd * (sizeof(double) + sizeof(float)), hipMemcpyHostToDevice,
                                   c->stream));
         STS_TRY(c, hipEventRecord(c->u_event, c->stream));
         c->u_event_live = true;
         g.uptr = c->dU;
+        g.uptr_f = reinterpret_cast<const float *>(c->dU + nd);
     }
     int sorted = c->cur, hb = 8;
     g.hb = sts_radix_bits(sort_shape(c)) * sort_passes(c); // the bucket bits the sort below uses
@@ -686,7 +693,7 @@ sts_status sts_truncate(sts_ctx *c)
     }
     // large states: estimate this step's cut on a sample of tiles first, so
     // that the histogram pass copies a narrow window around it
-    if (tiled && c->gate.m >= 1 && c->gate.m <= 3 && c->n_bound >= STS_SAMPLE_MIN)
+    if (tiled && c->gate.m >= 1 && c->gate.m <= 4 && c->n_bound >= STS_SAMPLE_MIN)
         STS_LAUNCH(c, STS_K_SAMPLE, launch_group_sample(c->prec, c->gate, b, c->stream));
     b.predict = tiled ? 1 : 0; // the histogram pass also extracts the predicted window
     // and keeps the candidates above it, so that a step whose cut falls in

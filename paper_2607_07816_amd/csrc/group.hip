@@ -19,6 +19,8 @@ hipError_t group_c128_small_extract_tiles(const GateArg &g, const PassBufs &b, i
 hipError_t group_c64_small_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t group_c128_small_sample(const GateArg &g, const PassBufs &b, hipStream_t s);
 hipError_t group_c64_small_sample(const GateArg &g, const PassBufs &b, hipStream_t s);
+hipError_t group_c128_large_sample(const GateArg &g, const PassBufs &b, hipStream_t s);
+hipError_t group_c64_large_sample(const GateArg &g, const PassBufs &b, hipStream_t s);
 hipError_t group_c128_small_emit_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t group_c64_small_emit_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
 hipError_t group_c128_large_extract_tiles(const GateArg &g, const PassBufs &b, int tiles, hipStream_t s);
@@ -61,6 +63,7 @@ hipError_t launch_group_emit_tiles(int prec, const GateArg &g, const PassBufs &b
 
 hipError_t launch_group_sample(int prec, const GateArg &g, const PassBufs &b, hipStream_t s)
 {
-    if (g.m < 1 || g.m > 3) return hipErrorInvalidValue; // tiled gates of 1..3 qubits only
+    if (g.m < 1 || g.m > 4) return hipErrorInvalidValue; // tiled gates of 1..4 qubits only
+    if (g.m == 4) return prec == 0 ? group_c128_large_sample(g, b, s) : group_c64_large_sample(g, b, s);
     return prec == 0 ? group_c128_small_sample(g, b, s) : group_c64_small_sample(g, b, s);
 }

@@ -49,3 +49,11 @@ hipError_t group_c128_large_emit_tiles(const GateArg &g, const PassBufs &b, int 
     }
     return hipErrorInvalidValue;
 }
+
+hipError_t group_c128_large_sample(const GateArg &g, const PassBufs &b, hipStream_t s)
+{
+    switch (g.m) {
+    case 4: return sample_m<double2, 4>(g, b, s);
+    }
+    return hipErrorInvalidValue;
+}

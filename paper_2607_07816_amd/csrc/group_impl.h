@@ -106,27 +106,36 @@ __device__ __forceinline__ void load_group(const GateArg &g, const u64 *__restri
     }
 }
 
+// a load through the constant address space: the matrix of a 4- or 5-qubit
+// gate is read-only while a kernel runs and the same in every lane, so its
+// entries come in by scalar loads (a plain pointer may alias the kernel's
+// stores, and its loads would each wait in the vector memory pipe)
+template <typename T> __device__ __forceinline__ T ld_const(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // entry U[i][j] in the arithmetic type R of the amplitudes (FP32 entries
-// were rounded once on the host; m >= 4 reads the FP64 copy in device memory)
+// were rounded once on the host; m >= 4 reads the copies in device memory)
 template <typename R, int M> struct UEntry;
 template <int M> struct UEntry<double, M> {
     static __device__ __forceinline__ double re(const GateArg &g, int i, int j)
     {
-        return M <= 3 ? g.ur[i * (1 << M) + j] : g.uptr[2 * (i * (1 << M) + j)];
+        return M <= 3 ? g.ur[i * (1 << M) + j] : ld_const(&g.uptr[2 * (i * (1 << M) + j)]);
     }
     static __device__ __forceinline__ double im(const GateArg &g, int i, int j)
     {
-        return M <= 3 ? g.ui[i * (1 << M) + j] : g.uptr[2 * (i * (1 << M) + j) + 1];
+        return M <= 3 ? g.ui[i * (1 << M) + j] : ld_const(&g.uptr[2 * (i * (1 << M) + j) + 1]);
     }
 };
 template <int M> struct UEntry<float, M> {
     static __device__ __forceinline__ float re(const GateArg &g, int i, int j)
     {
-        return M <= 3 ? g.fr[i * (1 << M) + j] : (float)g.uptr[2 * (i * (1 << M) + j)];
+        return M <= 3 ? g.fr[i * (1 << M) + j] : ld_const(&g.uptr_f[2 * (i * (1 << M) + j)]);
     }
     static __device__ __forceinline__ float im(const GateArg &g, int i, int j)
     {
-        return M <= 3 ? g.fi[i * (1 << M) + j] : (float)g.uptr[2 * (i * (1 << M) + j) + 1];
+        return M <= 3 ? g.fi[i * (1 << M) + j] : ld_const(&g.uptr_f[2 * (i * (1 << M) + j) + 1]);
     }
 };
 
@@ -666,8 +675,10 @@ __device__ __forceinline__ void flush_w2(const PassBufs &b, u64 *s_w2hi, u64 *s_
 // cut exponent (ctl->e_pred) also go to the tile's side-buffer slab, and the
 // tile's candidates above it are counted: when this step's cut exponent turns
 // out the same, the extraction pass has nothing left to do.
+// five workgroups per CU for gates of up to 3 qubits; a 4-qubit group (16
+// members) needs more registers, and three keep it out of scratch memory
 template <typename AT, int M>
-__global__ void __launch_bounds__(STS_WG, 5) k_tile_hist(const GateArg *__restrict__ gp, PassBufs b)
+__global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
     __shared__ TileSmem<AT> s;

@@ -22,6 +22,7 @@ struct GateArg {
     float fi[64];
     u64 dep[8];         // dep[i]: pattern i deposited on the gate's qubits (m <= 3)
     const double *uptr; // m >= 4
+    const float *uptr_f; // m >= 4: the same rounded to FP32 (nearest-even)
 };
 
 // Device buffers a grouping pass reads and writes.
