@@ -62,11 +62,60 @@ template <typename AT, int M> __device__ __forceinline__ void group_clear(Group<
     }
 }
 
+// Complex64 groups of 4-qubit gates are built differently. Such a group has
+// two of its 16 members on average, and a member's pattern is only known at
+// run time, so placing it in a register array takes a 16-way select and the
+// product a dense 16 x 16 pass. Instead the group holds its 16 outputs, and
+// each member found adds its column of U (read from LDS by the member's
+// pattern) times its amplitude: outputs sum the members in the order the
+// group scan finds them, the same in every pass of a step (the FP32 path is
+// held to a tolerance, not to the FP64 operation order).
+template <typename AT, int M> struct SparseGroup {
+    static constexpr bool value = false;
+};
+template <> struct SparseGroup<float2, 4> {
+    static constexpr bool value = true;
+};
+
+// the gate's matrix in LDS, U[i][j] at [16 i + j] (complex64, 4 qubits)
+__device__ __forceinline__ float2 *gate_table_c64_4()
+{
+    __shared__ float2 t[256];
+    return t;
+}
+
+// every kernel that builds groups calls this first, with every thread
+template <typename AT, int M> __device__ __forceinline__ void stage_gate(const GateArg &g)
+{
+    if constexpr (SparseGroup<AT, M>::value) {
+        float2 *t = gate_table_c64_4();
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) {
+            float2 u;
+            u.x = g.uptr_f[2 * k];
+            u.y = g.uptr_f[2 * k + 1];
+            t[k] = u;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename AT, int M> __device__ __forceinline__ void group_set(Group<AT, M> &G, u32 j, AT a)
 {
+    if constexpr (SparseGroup<AT, M>::value) {
+        const float2 *t = gate_table_c64_4();
 #pragma unroll
-    for (int jj = 0; jj < (1 << M); ++jj)
-        if (jj == (int)j) G.v[jj] = a;
+        for (int i = 0; i < 16; ++i) {
+            const float2 u = t[16 * i + (int)j];
+            G.v[i].x = __builtin_fmaf(u.x, a.x, G.v[i].x);
+            G.v[i].x = __builtin_fmaf(-u.y, a.y, G.v[i].x);
+            G.v[i].y = __builtin_fmaf(u.x, a.y, G.v[i].y);
+            G.v[i].y = __builtin_fmaf(u.y, a.x, G.v[i].y);
+        }
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < (1 << M); ++jj)
+            if (jj == (int)j) G.v[jj] = a;
+    }
     G.present |= 1u << j;
 }
 
@@ -145,6 +194,7 @@ __device__ __forceinline__ AT group_out(const GateArg &g, const Group<AT, M> &G,
 {
     typedef typename Scalar<AT>::T R;
     if (M == 0) return G.v[0];
+    if constexpr (SparseGroup<AT, M>::value) return G.v[i]; // accumulated by group_set
     R ar = (R)0, ai = (R)0;
     if (sizeof(R) == 4) {
         // complex64: fused multiply-adds (the FP32 path is held to a
@@ -199,6 +249,7 @@ template <typename AT, int M>
 __global__ void __launch_bounds__(STS_WG) k_group_hist(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
+    stage_gate<AT, M>(g);
     __shared__ u32 s_cnt[STS_NBIN];
     __shared__ u64 s_hi[STS_NBIN];
     __shared__ u64 s_lo[STS_NBIN];
@@ -294,6 +345,7 @@ template <typename AT, int M, int KIND>
 __global__ void __launch_bounds__(STS_WG) k_group_compact(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
+    stage_gate<AT, M>(g);
     typedef typename Scalar<AT>::T R;
     constexpr int IT = STS_GROUP_ITEMS;
     __shared__ u32 s_tile;
@@ -681,6 +733,7 @@ template <typename AT, int M>
 __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
+    stage_gate<AT, M>(g);
     __shared__ TileSmem<AT> s;
     __shared__ u64 s_hi[TT_SLOTS]; // sum of mantissa >> 26
     __shared__ u64 s_lo[TT_SLOTS]; // sum of mantissa & (2^26-1), plus count << 44
@@ -913,6 +966,7 @@ template <typename AT, int M>
 __global__ void __launch_bounds__(STS_WG) k_tile_sample(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
+    stage_gate<AT, M>(g);
     constexpr int SPAN = STS_SAMPLE_SPAN; // inputs per workgroup, from a tile's start
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_c[STS_SW_NB];
@@ -1085,6 +1139,7 @@ template <typename AT, int M>
 __global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
+    stage_gate<AT, M>(g);
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_above, s_side;
     const int tid = threadIdx.x;
@@ -1222,6 +1277,7 @@ template <typename AT, int M>
 __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict__ gp, PassBufs b)
 {
     const GateArg &g = *gp;
+    stage_gate<AT, M>(g);
     __shared__ TileSmem<AT> s;
     __shared__ u32 s_out;
     const int tid = threadIdx.x;
