@@ -450,7 +450,8 @@ sts_status materialise(sts_ctx *c)
     b.materialise = 1;
     if (use_tiles(c, c->gate.m)) {
         const int tt = (int)std::max<u64>(ceil_div(c->n_bound, 2048), 1);
-        STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_GROUP_EXTRACT,
+                   launch_group_extract_tiles(c->prec, c->gate, b, std::min(tt, 2048), c->stream));
         STS_LAUNCH(c, STS_K_TILE_KEPT, launch_tile_kept(b, tt, c->stream));
         STS_LAUNCH(c, STS_K_TILE_SCAN, launch_tile_scan(b, tt, c->stream));
         STS_LAUNCH(c, STS_K_GROUP_EMIT, launch_group_emit_tiles(c->prec, c->gate, b, tt, c->stream));
@@ -708,7 +709,8 @@ sts_status sts_truncate(sts_ctx *c)
         if (!c->hctl->keep_all && c->hctl->sub_count > c->scap) return refuse_step(c);
     }
     if (tiled) {
-        STS_LAUNCH(c, STS_K_GROUP_EXTRACT, launch_group_extract_tiles(c->prec, c->gate, b, tt, c->stream));
+        STS_LAUNCH(c, STS_K_GROUP_EXTRACT,
+                   launch_group_extract_tiles(c->prec, c->gate, b, std::min(tt, 2048), c->stream));
     } else {
         b.epoch = next_epoch(c);
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT,

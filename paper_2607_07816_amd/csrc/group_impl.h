@@ -1146,63 +1146,65 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restri
     DevCtl *ctl = b.ctl;
     const u64 n = *b.n_in;
     const u64 ntiles = (n + TT_TG - 1) / TT_TG;
-    const u64 tile = blockIdx.x;
     if (!b.materialise && ctl->pred_hit) return; // the histogram pass already did this
-    if (tile == 0 && tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         ctl->side_dense = 0;
         ctl->side_ntiles = ntiles;
         ctl->side_slab_shift = 11 + M;
         ctl->side_spt_log2 = 0;
     }
-    if (tile >= ntiles) return;
     const bool all = b.materialise || ctl->keep_all;
     const int e_star = ctl->e_star;
     const u64 *keys = b.keys;
     const AT *amps = (const AT *)b.amps;
-    const u64 base = tile * TT_TG;
-    const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
-    const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
-    if (tid == 0) {
-        s_above = 0;
-        s_side = 0;
-    }
-    stage_tile<AT, M>(s, g, keys, amps, lo, hi);
-    __syncthreads();
-    const u64 slab = tile << (11 + M);
-    u32 above = 0;
+    // a grid of at most a few thousand workgroups walks the tiles, so that
+    // the launch costs little when the window held the cut and it exits
+    for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const u64 base = tile * TT_TG;
+        const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
+        const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
+        if (tid == 0) {
+            s_above = 0;
+            s_side = 0;
+        }
+        stage_tile<AT, M>(s, g, keys, amps, lo, hi);
+        __syncthreads();
+        const u64 slab = tile << (11 + M);
+        u32 above = 0;
 #pragma unroll 1
-    for (int k = 0; k < TT_IT; ++k) {
-        const u64 e = base + (u64)k * STS_WG + tid;
-        Group<AT, M> G;
-        tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
-        u64 wbs[1 << M];
-        u32 sidebits = 0;
+        for (int k = 0; k < TT_IT; ++k) {
+            const u64 e = base + (u64)k * STS_WG + tid;
+            Group<AT, M> G;
+            tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
+            u64 wbs[1 << M];
+            u32 sidebits = 0;
 #pragma unroll Unroll<M>::value
-        for (int i = 0; i < (1 << M); ++i) {
-            const AT o = group_out<AT, M>(g, G, i);
-            const bool cand = G.present && (M == 0 || nonzero(o));
-            const u64 wb = weight_bits(o);
-            wbs[i] = wb;
-            const int ex = (int)(wb >> 52);
-            above += (cand && (all || ex > e_star)) ? 1u : 0u;
-            sidebits |= (cand && !all && ex == e_star) ? (1u << i) : 0u;
-        }
-        u32 at = wave_claim_n<M + 1>((u32)__popc(sidebits), &s_side);
-#pragma unroll Unroll<M>::value
-        for (int i = 0; i < (1 << M); ++i) {
-            if (!((sidebits >> i) & 1u)) continue;
-            if (slab + at < b.side_cap) {
-                b.side_key[slab + at] = G.rest | deposit_bits<M>((u32)i, g);
-                b.side_w[slab + at] = wbs[i];
+            for (int i = 0; i < (1 << M); ++i) {
+                const AT o = group_out<AT, M>(g, G, i);
+                const bool cand = G.present && (M == 0 || nonzero(o));
+                const u64 wb = weight_bits(o);
+                wbs[i] = wb;
+                const int ex = (int)(wb >> 52);
+                above += (cand && (all || ex > e_star)) ? 1u : 0u;
+                sidebits |= (cand && !all && ex == e_star) ? (1u << i) : 0u;
             }
-            ++at;
+            u32 at = wave_claim_n<M + 1>((u32)__popc(sidebits), &s_side);
+#pragma unroll Unroll<M>::value
+            for (int i = 0; i < (1 << M); ++i) {
+                if (!((sidebits >> i) & 1u)) continue;
+                if (slab + at < b.side_cap) {
+                    b.side_key[slab + at] = G.rest | deposit_bits<M>((u32)i, g);
+                    b.side_w[slab + at] = wbs[i];
+                }
+                ++at;
+            }
         }
-    }
-    atomicAdd(&s_above, above);
-    __syncthreads();
-    if (tid == 0) {
-        b.t_above[tile] = s_above;
-        b.t_side[tile] = s_side;
+        atomicAdd(&s_above, above);
+        __syncthreads();
+        if (tid == 0) {
+            b.t_above[tile] = s_above;
+            b.t_side[tile] = s_side;
+        }
     }
 }
 
