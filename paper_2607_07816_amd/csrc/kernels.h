@@ -182,6 +182,6 @@ inline u64 sts_compact_groups(u64 n, int m)
 #define STS_SW_EXPS 8                            // exponent fields the sampling bins cover
 #define STS_SW_NB (STS_SW_EXPS << STS_SW_FB)     // sampling bins (256)
 #define STS_SW_BANKS 16                          // copies of the sampling bins in device memory
-#define STS_SAMPLE_TILES 512                     // tiles the sampling pass runs the gate on
+#define STS_SAMPLE_TILES 256                     // tiles the sampling pass runs the gate on
 #define STS_SAMPLE_SPAN 512                      // inputs of each, from the tile's start
 #define STS_SAMPLE_MIN (1ull << 22)              // terms from which a step samples first
