@@ -58,6 +58,7 @@ struct DevCtl {
     int e_pred;          // cut exponent of the previous truncation (-1: none)
     int pred_hit;        // the histogram pass's side-buffer window holds this truncation's cut
     int w2_mode;         // the histogram pass binned a sampled window for level 2 (h2w)
+    int l2_done;         // the level-1 pick also picked level 2 from those bins
     // window of weights [w_lo, w_hi] (bit patterns, one exponent field e_w)
     // that the histogram pass copies to the side buffer: set for this step by
     // the sampling pass (w_mode = 1), else the octave of e_pred

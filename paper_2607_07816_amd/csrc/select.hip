@@ -130,6 +130,125 @@ __device__ inline double wl_to_double(u64 a)
     return ldexp((double)mant, lsb - 1074);
 }
 
+// Subset of the rank order still holding the cut: the terms of exponent e*
+// whose rank key V has the high part vpre above bit vshift.
+struct Sub {
+    u64 cnt_before; // terms ranked before the subset
+    u128 mb;        // their mantissa sum inside e* (units 2^(max(e*,1)-1075))
+    u128 vpre;
+    int vshift;
+    u64 count;      // terms in the subset
+};
+
+__device__ inline void sub_load(Sub &s, const DevCtl *ctl)
+{
+    s.cnt_before = ctl->cnt_before;
+    s.mb = make128(ctl->mb_lo, ctl->mb_hi);
+    s.vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
+    s.vshift = ctl->vshift;
+    s.count = ctl->sub_count;
+}
+
+__device__ inline void sub_store(const Sub &s, DevCtl *ctl)
+{
+    ctl->cnt_before = s.cnt_before;
+    ctl->mb_lo = (u64)s.mb;
+    ctl->mb_hi = (u64)(s.mb >> 64);
+    ctl->vpre_lo = (u64)s.vpre;
+    ctl->vpre_hi = (u64)(s.vpre >> 64);
+    ctl->vshift = s.vshift;
+    ctl->sub_count = s.count;
+}
+
+// Pick the first digit (ascending = rank order) where the rule is met, over
+// 2048 bins held in (cnt[], hi[], lo[]) - global (agent loads) or LDS - by NT
+// threads, and narrow *sub to it. K, R: the rule (R all ones = no p-mass).
+// Returns false if no digit qualifies.
+template <int NT>
+__device__ bool pick_digit(const u64 *cntp, const u64 *hip_, const u64 *lop, bool agent, u64 K, u128 R, int dw,
+                           Sub *sub, u128 *s_m, u64 *s_c, u32 *s_hit)
+{
+    constexpr int PER = STS_NBIN / NT;
+    const int t = threadIdx.x;
+    u64 c[PER];
+    u128 ms[PER];
+    u64 cc = 0;
+    u128 mm = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int d = PER * t + k;
+        if (agent) {
+            c[k] = ld_agent(&cntp[d]);
+            ms[k] = ((u128)ld_agent(&hip_[d]) << 26) + (u128)ld_agent(&lop[d]);
+        } else {
+            c[k] = cntp[d];
+            ms[k] = ((u128)hip_[d] << 26) + (u128)lop[d];
+        }
+        cc += c[k];
+        mm += ms[k];
+    }
+    const u64 own_c = cc;
+    const u128 own_m = mm;
+    s_c[t] = cc;
+    s_m[t] = mm;
+    if (t == 0) *s_hit = 0xffffffffu;
+    __syncthreads();
+    for (int d = 1; d < NT; d <<= 1) {
+        u64 oc = 0;
+        u128 om = 0;
+        if (t >= d) {
+            oc = s_c[t - d];
+            om = s_m[t - d];
+        }
+        __syncthreads();
+        if (t >= d) {
+            cc += oc;
+            mm += om;
+            s_c[t] = cc;
+            s_m[t] = mm;
+        }
+        __syncthreads();
+    }
+    // exclusive prefix of this thread's bins, from the subset's start
+    u64 cnt = sub->cnt_before + (cc - own_c);
+    u128 m = sub->mb + (mm - own_m);
+    u32 hit = 0xffffffffu;
+    u64 cnt_hit = 0;
+    u128 m_hit = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (hit == 0xffffffffu && c[k]) {
+            const bool hk = K > 0 && cnt + c[k] >= K;
+            const bool hp = m + ms[k] >= R;
+            if (hk || hp) {
+                hit = (u32)(PER * t + k);
+                cnt_hit = cnt;
+                m_hit = m;
+            } else {
+                cnt += c[k];
+                m += ms[k];
+            }
+        }
+    }
+    if (hit != 0xffffffffu) atomicMin(s_hit, hit);
+    __syncthreads();
+    const u32 first = *s_hit;
+    if (first == 0xffffffffu) {
+        __syncthreads();
+        return false;
+    }
+    if (hit == first) {
+        const int k = (int)first - PER * t;
+        sub->vpre = (sub->vpre << dw) | (u128)first;
+        sub->vshift -= dw;
+        sub->cnt_before = cnt_hit;
+        sub->mb = m_hit;
+        sub->count = c[k];
+    }
+    __syncthreads();
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // level 1: one workgroup of 256 threads. Thread t owns the eight exponent
 // bins 2047-8t .. 2040-8t (descending weight order). The bins that hold
@@ -141,11 +260,14 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
 {
     __shared__ u32 s_e[STS_NBIN];   // the non-empty bins in rank order: exponent field,
     __shared__ u64 s_c[STS_NBIN];   // count,
-    __shared__ u64 s_lo[STS_NBIN];  // mantissa sum (low, high words)
+    __shared__ __attribute__((aligned(16))) u64 s_lo[STS_NBIN]; // mantissa sum (low, high words)
     __shared__ u64 s_hi[STS_NBIN];
     __shared__ u32 s_scan[4];
     __shared__ u64 s_bw[4], s_bk[4];
     __shared__ u64 s_w[6];
+    __shared__ Sub s_sub;   // level 2 of a sampled window that holds the cut
+    __shared__ u32 s_fine, s_hit2;
+    __shared__ u64 s_sub_R_lo, s_sub_R_hi;
     const int t = threadIdx.x;
     DevCtl *ctl = b.ctl;
     u64 *h1 = b.h1;
@@ -153,6 +275,7 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     const int w_mode = ctl->w_mode;
     const int e_w = predicted ? (w_mode ? ctl->e_w : ctl->e_pred) : -1;
     if (t < 6) s_w[t] = 0;
+    if (t == 0) s_fine = 0;
 
     // own bins: every load issued before any is used
     u64 c[8], hi[8], lo[8];
@@ -342,6 +465,18 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
                     }
                 }
                 if (lane < STS_NL) ctl->S_excl.l[lane] = S;
+                if (lane == 0 && in_window && w_mode && predicted) {
+                    // the histogram pass binned this window for level 2: the
+                    // whole workgroup picks its digit below
+                    s_fine = 1;
+                    s_sub.cnt_before = cnt + ca;
+                    s_sub.mb = ma;
+                    s_sub.vpre = 0;
+                    s_sub.vshift = 116;
+                    s_sub.count = cw;
+                    s_sub_R_lo = R_lo;
+                    s_sub_R_hi = R_hi;
+                }
                 if (lane == 0) {
                     ctl->keep_all = 0;
                     ctl->pred_hit = in_window ? 1 : 0;
@@ -359,11 +494,32 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
             if (lane == 0) {
                 ctl->w2_mode = predicted && w_mode; // the histogram pass binned the window for level 2
                 ctl->w_mode = 0;                     // a window serves one step
+                ctl->l2_done = 0;
             }
         }
     }
     __syncthreads();
     for (int i = t; i < 3 * STS_NBIN; i += 256) h1[i] = 0;
+    if (s_fine) { // uniform
+        // level 2 from the window's bins (the side pass then has nothing to
+        // do); the bin lists above are done with, so their LDS serves the pick
+        const u128 R = make128(s_sub_R_lo, s_sub_R_hi);
+        u128 *s_m = reinterpret_cast<u128 *>(s_lo);
+        u64 *s_c2 = s_hi;
+        const bool ok = pick_digit<256>(b.h2w, b.h2w + STS_NBIN, b.h2w + 2 * STS_NBIN, true, ctl->K, R, 11, &s_sub,
+                                        s_m, s_c2, &s_hit2);
+        if (t == 0) {
+            if (ok) {
+                sub_store(s_sub, ctl);
+                ctl->level = 2;
+                for (int i = 0; i <= STS_SUB_REGIONS; ++i) st_agent(&b.sub_cnt[i * 32], 0u);
+                ctl->l2_done = 1;
+            } else {
+                atomicOr(&ctl->flags, STS_F_UNRESOLVED);
+            }
+        }
+        for (int i = t; i < 3 * STS_NBIN; i += 256) st_agent(&b.h2w[i], 0ull);
+    }
 }
 
 // The side buffer is either dense (entries [0, side_n)) or split into slabs
@@ -452,124 +608,6 @@ __device__ __forceinline__ u64 mant_of_v(u128 v, int e)
     return e ? (frac | (1ull << 52)) : frac;
 }
 
-// Subset of the rank order still holding the cut: the terms of exponent e*
-// whose rank key V has the high part vpre above bit vshift.
-struct Sub {
-    u64 cnt_before; // terms ranked before the subset
-    u128 mb;        // their mantissa sum inside e* (units 2^(max(e*,1)-1075))
-    u128 vpre;
-    int vshift;
-    u64 count;      // terms in the subset
-};
-
-__device__ inline void sub_load(Sub &s, const DevCtl *ctl)
-{
-    s.cnt_before = ctl->cnt_before;
-    s.mb = make128(ctl->mb_lo, ctl->mb_hi);
-    s.vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
-    s.vshift = ctl->vshift;
-    s.count = ctl->sub_count;
-}
-
-__device__ inline void sub_store(const Sub &s, DevCtl *ctl)
-{
-    ctl->cnt_before = s.cnt_before;
-    ctl->mb_lo = (u64)s.mb;
-    ctl->mb_hi = (u64)(s.mb >> 64);
-    ctl->vpre_lo = (u64)s.vpre;
-    ctl->vpre_hi = (u64)(s.vpre >> 64);
-    ctl->vshift = s.vshift;
-    ctl->sub_count = s.count;
-}
-
-// Pick the first digit (ascending = rank order) where the rule is met, over
-// 2048 bins held in (cnt[], hi[], lo[]) - global (agent loads) or LDS - by NT
-// threads, and narrow *sub to it. K, R: the rule (R all ones = no p-mass).
-// Returns false if no digit qualifies.
-template <int NT>
-__device__ bool pick_digit(const u64 *cntp, const u64 *hip_, const u64 *lop, bool agent, u64 K, u128 R, int dw,
-                           Sub *sub, u128 *s_m, u64 *s_c, u32 *s_hit)
-{
-    constexpr int PER = STS_NBIN / NT;
-    const int t = threadIdx.x;
-    u64 c[PER];
-    u128 ms[PER];
-    u64 cc = 0;
-    u128 mm = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int d = PER * t + k;
-        if (agent) {
-            c[k] = ld_agent(&cntp[d]);
-            ms[k] = ((u128)ld_agent(&hip_[d]) << 26) + (u128)ld_agent(&lop[d]);
-        } else {
-            c[k] = cntp[d];
-            ms[k] = ((u128)hip_[d] << 26) + (u128)lop[d];
-        }
-        cc += c[k];
-        mm += ms[k];
-    }
-    const u64 own_c = cc;
-    const u128 own_m = mm;
-    s_c[t] = cc;
-    s_m[t] = mm;
-    if (t == 0) *s_hit = 0xffffffffu;
-    __syncthreads();
-    for (int d = 1; d < NT; d <<= 1) {
-        u64 oc = 0;
-        u128 om = 0;
-        if (t >= d) {
-            oc = s_c[t - d];
-            om = s_m[t - d];
-        }
-        __syncthreads();
-        if (t >= d) {
-            cc += oc;
-            mm += om;
-            s_c[t] = cc;
-            s_m[t] = mm;
-        }
-        __syncthreads();
-    }
-    // exclusive prefix of this thread's bins, from the subset's start
-    u64 cnt = sub->cnt_before + (cc - own_c);
-    u128 m = sub->mb + (mm - own_m);
-    u32 hit = 0xffffffffu;
-    u64 cnt_hit = 0;
-    u128 m_hit = 0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        if (hit == 0xffffffffu && c[k]) {
-            const bool hk = K > 0 && cnt + c[k] >= K;
-            const bool hp = m + ms[k] >= R;
-            if (hk || hp) {
-                hit = (u32)(PER * t + k);
-                cnt_hit = cnt;
-                m_hit = m;
-            } else {
-                cnt += c[k];
-                m += ms[k];
-            }
-        }
-    }
-    if (hit != 0xffffffffu) atomicMin(s_hit, hit);
-    __syncthreads();
-    const u32 first = *s_hit;
-    if (first == 0xffffffffu) {
-        __syncthreads();
-        return false;
-    }
-    if (hit == first) {
-        const int k = (int)first - PER * t;
-        sub->vpre = (sub->vpre << dw) | (u128)first;
-        sub->vshift -= dw;
-        sub->cnt_before = cnt_hit;
-        sub->mb = m_hit;
-        sub->count = c[k];
-    }
-    __syncthreads();
-    return true;
-}
 
 // ---------------------------------------------------------------------------
 // level 2 over the side buffer (many workgroups), pick by the last one
@@ -657,6 +695,9 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
     __shared__ Sub s_sub;
     DevCtl *ctl = b.ctl;
     const int keep_all = ctl->keep_all, w2 = ctl->w2_mode;
+    // the level-1 pick already picked level 2 from the histogram pass's
+    // window bins
+    if (ctl->l2_done) return;
     // the histogram pass binned a sampled window that holds the cut: its
     // level-2 bins are complete, and only the pick is left
     const bool fine = w2 && ctl->pred_hit && !keep_all;
