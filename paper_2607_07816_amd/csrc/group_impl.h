@@ -512,6 +512,34 @@ __device__ __forceinline__ void stage_tile(TileSmem<AT> &s, const GateArg &g, co
     }
 }
 
+// whether term e (global index) leads its group: no earlier term of the
+// staged tile [lo, hi), or before it, has the same rest of key (the backward
+// half of tile_group's scan)
+template <int M>
+__device__ __forceinline__ bool tile_leads(const unsigned short *bkt, const u64 *skey, const GateArg &g,
+                                           const u64 *__restrict__ keys, u64 lo, u64 n, u64 e)
+{
+    if (e >= n) return false;
+    if (M == 0) return true;
+    const int li = (int)(e - lo);
+    const u64 nm = g.notmask;
+    const u64 rest = skey[li] & nm;
+    const u32 b = bkt[li];
+    int p = li - 1;
+    for (; p >= 0; --p) {
+        if (bkt[p] != b) return true;
+        if ((skey[p] & nm) == rest) return false;
+    }
+    // the run goes on below the staged range
+    const int sh = 64 - g.hb;
+    for (u64 q = lo; q > 0; --q) {
+        const u64 kq = keys[q - 1];
+        if (tile_bucket(kq, nm, sh) != b) break;
+        if ((kq & nm) == rest) return false;
+    }
+    return true;
+}
+
 // the group led by term e (global index), from the staged tile [lo, hi).
 // Both scans walk LDS with 32-bit local indices; a run that reaches the edge
 // of the staged range (rare: the halo is 64 terms) continues in global memory
@@ -742,6 +770,11 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
     // its exponent (mantissa sum >> 26, & (2^26-1)); candidates inside it, the
     // same two sums
     __shared__ u64 s_wacc[6];
+    // 4-qubit gates: the tile's group leaders, listed so that every lane of
+    // the output loop has a group (about half the terms lead one, and the
+    // loop over a group's 16 outputs runs for the whole wave)
+    __shared__ unsigned short s_lead[M >= 4 ? TT_TG : 1];
+    __shared__ u32 s_nlead;
     // level-2 bins of a sampled window (sums split at bit 20, count << 44)
     __shared__ u64 s_w2hi[TT_W2], s_w2lo[TT_W2];
     for (int i = threadIdx.x; i < TT_SLOTS; i += STS_WG) {
@@ -820,8 +853,21 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
         const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
         const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
         __syncthreads(); // previous tile done with the LDS
+        if (M >= 4 && threadIdx.x == 0) s_nlead = 0;
         stage_tile<AT, M>(s, g, keys, amps, lo, hi);
         __syncthreads();
+        int rounds = TT_IT;
+        if constexpr (M >= 4) {
+#pragma unroll 1
+            for (int k = 0; k < TT_IT; ++k) {
+                const u64 e = base + (u64)k * STS_WG + threadIdx.x;
+                const bool lead = tile_leads<M>(s.bkt, s.key, g, keys, lo, n, e);
+                const u32 at = wave_claim(lead, &s_nlead);
+                if (lead) s_lead[at] = (unsigned short)(e - base);
+            }
+            __syncthreads();
+            rounds = (int)((s_nlead + STS_WG - 1) / STS_WG);
+        }
         const u64 slab = ((tile << 2) + (u64)wv) << (9 + M);
         const bool slab_fits = slab + (512ull << M) <= b.side_cap;
         const bool keep_above = predict && b.copy && slab_fits;
@@ -831,8 +877,12 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
         AT *const sa = (AT *)b.side_amp + slab;
         u32 c_in = 0, c_ab = 0; // the wave's claims so far (the same in every lane)
 #pragma unroll 1
-        for (int k = 0; k < TT_IT; ++k) {
-            const u64 e = base + (u64)k * STS_WG + threadIdx.x;
+        for (int k = 0; k < rounds; ++k) {
+            u64 e = base + (u64)k * STS_WG + threadIdx.x;
+            if constexpr (M >= 4) {
+                const u32 j = (u32)k * STS_WG + threadIdx.x;
+                e = j < s_nlead ? base + s_lead[j] : n; // n: no group
+            }
             Group<AT, M> G;
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
 #pragma unroll Unroll<M>::value
