@@ -762,6 +762,7 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
 {
     const GateArg &g = *gp;
     stage_gate<AT, M>(g);
+    constexpr bool kLeadList = M >= 4;
     __shared__ TileSmem<AT> s;
     __shared__ u64 s_hi[TT_SLOTS]; // sum of mantissa >> 26
     __shared__ u64 s_lo[TT_SLOTS]; // sum of mantissa & (2^26-1), plus count << 44
@@ -773,7 +774,7 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
     // 4-qubit gates: the tile's group leaders, listed so that every lane of
     // the output loop has a group (about half the terms lead one, and the
     // loop over a group's 16 outputs runs for the whole wave)
-    __shared__ unsigned short s_lead[M >= 4 ? TT_TG : 1];
+    __shared__ unsigned short s_lead[kLeadList ? TT_TG : 1];
     __shared__ u32 s_nlead;
     // level-2 bins of a sampled window (sums split at bit 20, count << 44)
     __shared__ u64 s_w2hi[TT_W2], s_w2lo[TT_W2];
@@ -853,11 +854,11 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
         const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
         const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
         __syncthreads(); // previous tile done with the LDS
-        if (M >= 4 && threadIdx.x == 0) s_nlead = 0;
+        if (kLeadList && threadIdx.x == 0) s_nlead = 0;
         stage_tile<AT, M>(s, g, keys, amps, lo, hi);
         __syncthreads();
         int rounds = TT_IT;
-        if constexpr (M >= 4) {
+        if constexpr (kLeadList) {
 #pragma unroll 1
             for (int k = 0; k < TT_IT; ++k) {
                 const u64 e = base + (u64)k * STS_WG + threadIdx.x;
@@ -879,7 +880,7 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
 #pragma unroll 1
         for (int k = 0; k < rounds; ++k) {
             u64 e = base + (u64)k * STS_WG + threadIdx.x;
-            if constexpr (M >= 4) {
+            if constexpr (kLeadList) {
                 const u32 j = (u32)k * STS_WG + threadIdx.x;
                 e = j < s_nlead ? base + s_lead[j] : n; // n: no group
             }
