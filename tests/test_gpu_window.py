@@ -114,3 +114,37 @@ def test_window_ties_at_the_cut():
     K = len(keys) + 77777
     say("tie step c128")
     check(*one_step(keys, amps, 36, (0, 20), U, K, 0.0, "c128"), "c128")
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_four_qubit_gate_sampled_window(prec):
+    # a 4-qubit gate on a state of 2^22+ terms takes the LDS-tiled passes
+    # (capacity twice the state) and the sampling pass; complex64 groups
+    # accumulate their outputs member by member, and the histogram pass lists
+    # each tile's group leaders first
+    from paper_2607_07816_amd import _lib
+    rng = np.random.default_rng(4404)
+    n = 40
+    keys, amps = random_state(rng, n, N_BIG)
+    # one term in eight gets a partner that differs on one of the gate's qubits
+    qs = (2, 9, 17, 33)
+    pick = rng.choice(len(keys), size=len(keys) // 8, replace=False)
+    keys = np.concatenate([keys, keys[pick] ^ np.uint64(1 << 17)])
+    amps = np.concatenate([amps, amps[pick] * np.exp(1j * rng.uniform(0, 2 * np.pi, len(pick)))])
+    keys, first = np.unique(keys, return_index=True)
+    amps = amps[first]
+    amps /= np.linalg.norm(amps)
+    if prec == "c64":
+        amps = amps.astype(np.complex64).astype(np.complex128)
+    U = C.haar_unitary(rng, 16)
+    K = len(keys)
+    say(f"4-qubit window step {prec} N={len(keys)} K={K}")
+    with _lib.State(n, K=K, p=0.0, precision=prec, capacity=2 * len(keys) + 4096) as st:
+        st.load_terms(keys, amps)
+        st.apply_gate(qs, U)
+        st.truncate()
+        kg, ag = st.read_terms()
+        stats = st.stats()
+    ko, ao, info = CO.step(keys, amps, qs, U, K, 0.0, True, CO.host_threads())
+    ko, ao = CO.sorted_terms(ko, ao)
+    check(kg, ag, stats, ko, ao, info, prec)
