@@ -62,25 +62,27 @@ template <typename AT, int M> __device__ __forceinline__ void group_clear(Group<
     }
 }
 
-// Complex64 groups of 4-qubit gates are built differently. Such a group has
-// two of its 16 members on average, and a member's pattern is only known at
-// run time, so placing it in a register array takes a 16-way select and the
-// product a dense 16 x 16 pass. Instead the group holds its 16 outputs, and
-// each member found adds its column of U (read from LDS by the member's
-// pattern) times its amplitude: outputs sum the members in the order the
-// group scan finds them, the same in every pass of a step (the FP32 path is
-// held to a tolerance, not to the FP64 operation order).
+// Complex64 groups of 3- and 4-qubit gates are built differently. A group
+// has few members (about two of 8 or 16), and a member's pattern is only
+// known at run time, so placing it in a register array takes a 2^m-way
+// select and the product a dense 2^m x 2^m pass. Instead the group holds its
+// 2^m outputs, and each member found adds its column of U (read from LDS by
+// the member's pattern) times its amplitude. The outputs sum the members in
+// the order the group scan finds them: the same in every pass of a step, and
+// in every run, since every pass writes its terms in an order fixed by the
+// input (the FP32 path is held to a tolerance, not to the FP64 operation
+// order; for 1- and 2-qubit gates the dense product is the faster one).
 template <typename AT, int M> struct SparseGroup {
     static constexpr bool value = false;
 };
-template <> struct SparseGroup<float2, 4> {
-    static constexpr bool value = true;
+template <int M> struct SparseGroup<float2, M> {
+    static constexpr bool value = M >= 3 && M <= 4;
 };
 
-// the gate's matrix in LDS, U[i][j] at [16 i + j] (complex64, 4 qubits)
-__device__ __forceinline__ float2 *gate_table_c64_4()
+// the gate's matrix in LDS, U[i][j] at [2^m i + j] (complex64)
+template <int M> __device__ __forceinline__ float2 *gate_table_c64()
 {
-    __shared__ float2 t[256];
+    __shared__ float2 t[1 << (2 * M)];
     return t;
 }
 
@@ -88,11 +90,11 @@ __device__ __forceinline__ float2 *gate_table_c64_4()
 template <typename AT, int M> __device__ __forceinline__ void stage_gate(const GateArg &g)
 {
     if constexpr (SparseGroup<AT, M>::value) {
-        float2 *t = gate_table_c64_4();
-        for (int k = threadIdx.x; k < 256; k += blockDim.x) {
+        float2 *t = gate_table_c64<M>();
+        for (int k = threadIdx.x; k < (1 << (2 * M)); k += blockDim.x) {
             float2 u;
-            u.x = g.uptr_f[2 * k];
-            u.y = g.uptr_f[2 * k + 1];
+            u.x = M <= 3 ? g.fr[k] : g.uptr_f[2 * k];
+            u.y = M <= 3 ? g.fi[k] : g.uptr_f[2 * k + 1];
             t[k] = u;
         }
         __syncthreads();
@@ -102,10 +104,10 @@ template <typename AT, int M> __device__ __forceinline__ void stage_gate(const G
 template <typename AT, int M> __device__ __forceinline__ void group_set(Group<AT, M> &G, u32 j, AT a)
 {
     if constexpr (SparseGroup<AT, M>::value) {
-        const float2 *t = gate_table_c64_4();
+        const float2 *t = gate_table_c64<M>();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const float2 u = t[16 * i + (int)j];
+        for (int i = 0; i < (1 << M); ++i) {
+            const float2 u = t[(1 << M) * i + (int)j];
             G.v[i].x = __builtin_fmaf(u.x, a.x, G.v[i].x);
             G.v[i].x = __builtin_fmaf(-u.y, a.y, G.v[i].x);
             G.v[i].y = __builtin_fmaf(u.x, a.y, G.v[i].y);
@@ -775,7 +777,7 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
     // the output loop has a group (about half the terms lead one, and the
     // loop over a group's 16 outputs runs for the whole wave)
     __shared__ unsigned short s_lead[kLeadList ? TT_TG : 1];
-    __shared__ u32 s_nlead;
+    __shared__ u32 s_lscan[STS_WG / 64];
     // level-2 bins of a sampled window (sums split at bit 20, count << 44)
     __shared__ u64 s_w2hi[TT_W2], s_w2lo[TT_W2];
     for (int i = threadIdx.x; i < TT_SLOTS; i += STS_WG) {
@@ -854,20 +856,25 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
         const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
         const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
         __syncthreads(); // previous tile done with the LDS
-        if (kLeadList && threadIdx.x == 0) s_nlead = 0;
         stage_tile<AT, M>(s, g, keys, amps, lo, hi);
         __syncthreads();
         int rounds = TT_IT;
+        u32 nlead = 0; // the same in every thread
         if constexpr (kLeadList) {
+            // listed in term order (a block scan, not claims): the order in
+            // which the output loop meets the groups, and so the order of
+            // the survivors this step writes, is the same in every run
 #pragma unroll 1
             for (int k = 0; k < TT_IT; ++k) {
                 const u64 e = base + (u64)k * STS_WG + threadIdx.x;
                 const bool lead = tile_leads<M>(s.bkt, s.key, g, keys, lo, n, e);
-                const u32 at = wave_claim(lead, &s_nlead);
+                u32 tot;
+                const u32 at = nlead + block_excl_scan<u32, STS_WG>(lead ? 1u : 0u, s_lscan, &tot);
                 if (lead) s_lead[at] = (unsigned short)(e - base);
+                nlead += tot;
             }
             __syncthreads();
-            rounds = (int)((s_nlead + STS_WG - 1) / STS_WG);
+            rounds = (int)((nlead + STS_WG - 1) / STS_WG);
         }
         const u64 slab = ((tile << 2) + (u64)wv) << (9 + M);
         const bool slab_fits = slab + (512ull << M) <= b.side_cap;
@@ -882,7 +889,7 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
             u64 e = base + (u64)k * STS_WG + threadIdx.x;
             if constexpr (kLeadList) {
                 const u32 j = (u32)k * STS_WG + threadIdx.x;
-                e = j < s_nlead ? base + s_lead[j] : n; // n: no group
+                e = j < nlead ? base + s_lead[j] : n; // n: no group
             }
             Group<AT, M> G;
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
@@ -1278,7 +1285,7 @@ template <typename AT> __device__ __forceinline__ AT out_amp(AT o, bool rescale,
 // computing path of k_tile_emit.
 template <typename AT>
 __device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int spl, int shift, u64 out0, u64 thr_w,
-                                              u64 thr_k, bool rescale, double scale, u32 *s_out)
+                                              u64 thr_k, bool rescale, double scale, u32 *s_scan)
 {
     constexpr int UN = 4;
     const TileSlabs ab = tile_slabs(b.t_above, tile, spl, shift, true, b.side_cap);
@@ -1307,7 +1314,9 @@ __device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int s
             }
         }
     }
-    // the window's survivors after them, in claim order
+    // the window's survivors after them, in slab order (a block scan, so the
+    // order is the same in every run)
+    u32 run = 0;
     for (u32 j0 = 0; j0 < ns; j0 += STS_WG) {
         const u32 j = j0 + threadIdx.x;
         bool keep = false;
@@ -1318,11 +1327,13 @@ __device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int s
             k = b.side_key[i];
             keep = w > thr_w || (w == thr_w && k <= thr_k);
         }
-        const u64 at = out0 + na + wave_claim(keep, s_out);
+        u32 tot;
+        const u64 at = out0 + na + run + block_excl_scan<u32, STS_WG>(keep ? 1u : 0u, s_scan, &tot);
         if (keep && at < b.out_cap) {
             b.out_keys[at] = k;
             oa[at] = out_amp(sa[i], rescale, scale);
         }
+        run += tot;
     }
 }
 
@@ -1332,7 +1343,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
     const GateArg &g = *gp;
     stage_gate<AT, M>(g);
     __shared__ TileSmem<AT> s;
-    __shared__ u32 s_out;
+    __shared__ u32 s_scan[STS_WG / 64];
     const int tid = threadIdx.x;
     DevCtl *ctl = b.ctl;
     const u64 tile = blockIdx.x; // below the tile arrays' length (the launch's bound)
@@ -1349,9 +1360,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
     const bool rescale = !all && dropped;
     // the histogram pass kept this tile's survivors when its slabs fit
     if (b.copy && !all && hit && spl == 2 && shift == 9 + M && ((tile + 1) << (11 + M)) <= b.side_cap) {
-        if (tid == 0) s_out = 0;
-        __syncthreads();
-        tile_copy_out<AT>(b, tile, spl, shift, out0, thr_w, thr_k, rescale, scale, &s_out);
+        tile_copy_out<AT>(b, tile, spl, shift, out0, thr_w, thr_k, rescale, scale, s_scan);
         return;
     }
     const u64 *keys = b.keys;
@@ -1359,9 +1368,11 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
     const u64 base = tile * TT_TG;
     const u64 lo = base > (u64)TT_H ? base - TT_H : 0;
     const u64 hi = base + TT_TG + TT_H < n ? base + TT_TG + TT_H : n;
-    if (tid == 0) s_out = 0;
     stage_tile<AT, M>(s, g, keys, amps, lo, hi);
     __syncthreads();
+    // survivors in term order (a block scan per round, not claims): the new
+    // state's order, and so every later step's, is the same in every run
+    u32 run = 0;
 #pragma unroll 1
     for (int k = 0; k < TT_IT; ++k) {
         const u64 e = base + (u64)k * STS_WG + tid;
@@ -1379,7 +1390,9 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
                               (all || wb > thr_w || (wb == thr_w && key <= thr_k));
             keepbits |= keep ? (1u << i) : 0u;
         }
-        u32 at = wave_claim_n<M + 1>((u32)__popc(keepbits), &s_out);
+        u32 tot;
+        u32 at = run + block_excl_scan<u32, STS_WG>((u32)__popc(keepbits), s_scan, &tot);
+        run += tot;
 #pragma unroll Unroll<M>::value
         for (int i = 0; i < (1 << M); ++i) {
             if (!((keepbits >> i) & 1u)) continue;

@@ -287,6 +287,23 @@ def test_determinism(S):
     assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
 
 
+def test_determinism_fused_four_qubit_blocks(S):
+    # complex64 groups sum their members in the order the group scan meets
+    # them, so that order (the state's order after each step) must be the
+    # same in every run
+    from paper_2607_07816_amd import compile as CC
+    from paper_2607_07816_amd.run import run_circuit
+    c = CC.compile_circuit(C.peaked_circuit(30, 5, 0.03, 9, pairs="random", u3_layers=False), 4)
+    assert max(len(q) for q, _ in c.gates) == 4
+    outs = []
+    for _ in range(2):
+        st = run_circuit(c, K=20000, p=0.99, precision="c64", capacity=1 << 17)
+        outs.append(st.read_terms())
+        st.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1].view(np.uint64), outs[1][1].view(np.uint64))
+
+
 def test_argument_errors(S):
     with S.State(8, K=16, precision="c128", capacity=1024) as st:
         with pytest.raises(S.StsError):
