@@ -23,13 +23,6 @@ template <typename AT> struct Scalar;
 template <> struct Scalar<double2> { typedef double T; };
 template <> struct Scalar<float2> { typedef float T; };
 
-// the loops over a group's outputs are unrolled for gates of up to 4
-// qubits, so per-output arrays stay in registers (the 32-output case would
-// multiply the code size; 5-qubit gates take the untiled passes)
-template <int M> struct Unroll {
-    static constexpr int value = M <= 4 ? (1 << M) : 1;
-};
-
 template <typename AT, int M> struct Group {
     AT v[1 << M];
     u32 present; // bit j: member with pattern j exists (0: this thread leads no group)
@@ -76,7 +69,14 @@ template <typename AT, int M> struct SparseGroup {
     static constexpr bool value = false;
 };
 template <int M> struct SparseGroup<float2, M> {
-    static constexpr bool value = M >= 3 && M <= 4;
+    static constexpr bool value = M >= 3 && M <= 5;
+};
+
+// the loops over a group's outputs: unrolled for gates of up to 4 qubits,
+// and for complex64 5-qubit groups, whose 32 sums are registers indexed by
+// the loop (other 5-qubit groups are read by index from scratch memory)
+template <typename AT, int M> struct OutUnroll {
+    static constexpr int value = (M <= 4 || SparseGroup<AT, M>::value) ? (1 << M) : 1;
 };
 
 // the gate's matrix in LDS, U[i][j] at [2^m i + j] (complex64)
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(STS_WG) k_group_hist(const GateArg *__restrict
         Group<AT, M> G;
         load_group<AT, M>(g, keys, amps, idx, n, G);
         if (!G.present) continue;
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
         for (int i = 0; i < (1 << M); ++i) {
             const AT o = group_out<AT, M>(g, G, i);
             if (M > 0 && !nonzero(o)) continue;
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(STS_WG) k_group_compact(const GateArg *__restr
         Group<AT, M> G;
         load_group<AT, M>(g, keys, amps, idx, n, G);
         if (!G.present) continue;
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
         for (int i = 0; i < (1 << M); ++i) {
             const AT o = group_out<AT, M>(g, G, i);
             const u64 key = G.rest | deposit_bits<M>((u32)i, g);
@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(STS_WG) k_group_compact(const GateArg *__restr
         Group<AT, M> G;
         load_group<AT, M>(g, keys, amps, idx, n, G);
         if (!G.present) continue;
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
         for (int i = 0; i < (1 << M); ++i) {
             AT o = group_out<AT, M>(g, G, i);
             const u64 key = G.rest | deposit_bits<M>((u32)i, g);
@@ -893,7 +893,7 @@ __global__ void __launch_bounds__(STS_WG, M >= 4 ? 3 : 5) k_tile_hist(const Gate
             }
             Group<AT, M> G;
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
             for (int i = 0; i < (1 << M); ++i) {
                 const AT o = group_out<AT, M>(g, G, i);
                 const bool cand = G.present && (M == 0 || nonzero(o));
@@ -1075,7 +1075,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_sample(const GateArg *__restric
             const u64 e = base + (u64)k * STS_WG + threadIdx.x;
             Group<AT, M> G;
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e < end ? e : n, G);
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
             for (int i = 0; i < (1 << M); ++i) {
                 const AT o = group_out<AT, M>(g, G, i);
                 if (!G.present || !nonzero(o)) continue;
@@ -1236,7 +1236,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restri
             tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
             u64 wbs[1 << M];
             u32 sidebits = 0;
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
             for (int i = 0; i < (1 << M); ++i) {
                 const AT o = group_out<AT, M>(g, G, i);
                 const bool cand = G.present && (M == 0 || nonzero(o));
@@ -1247,7 +1247,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_extract(const GateArg *__restri
                 sidebits |= (cand && !all && ex == e_star) ? (1u << i) : 0u;
             }
             u32 at = wave_claim_n<M + 1>((u32)__popc(sidebits), &s_side);
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
             for (int i = 0; i < (1 << M); ++i) {
                 if (!((sidebits >> i) & 1u)) continue;
                 if (slab + at < b.side_cap) {
@@ -1380,7 +1380,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
         tile_group<AT, M>(s, g, keys, amps, lo, hi, n, e, G);
         AT os[1 << M];
         u32 keepbits = 0;
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
         for (int i = 0; i < (1 << M); ++i) {
             const AT o = group_out<AT, M>(g, G, i);
             os[i] = o;
@@ -1393,7 +1393,7 @@ __global__ void __launch_bounds__(STS_WG) k_tile_emit(const GateArg *__restrict_
         u32 tot;
         u32 at = run + block_excl_scan<u32, STS_WG>((u32)__popc(keepbits), s_scan, &tot);
         run += tot;
-#pragma unroll Unroll<M>::value
+#pragma unroll OutUnroll<AT, M>::value
         for (int i = 0; i < (1 << M); ++i) {
             if (!((keepbits >> i) & 1u)) continue;
             if (out0 + at < b.out_cap) {

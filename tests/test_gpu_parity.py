@@ -395,6 +395,38 @@ def test_five_qubit_cut_beyond_the_side_buffer(S):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("K", [3000, 0])
+def test_five_qubit_gate(S, prec, K):
+    # 5-qubit gates take the untiled passes; complex64 groups sum their 32
+    # outputs member by member (no scratch memory), FP64 ones keep the dense
+    # product in ascending member order
+    rng = np.random.default_rng(505 + K)
+    n, N = 22, 4000
+    keys, amps = random_state(rng, n, N)
+    # partners: one term in four gets a second member on the gate's qubits
+    qubits = (1, 4, 8, 13, 21)
+    pick = rng.choice(N, size=N // 4, replace=False)
+    keys = np.concatenate([keys, keys[pick] ^ np.uint64(1 << 8)])
+    amps = np.concatenate([amps, amps[pick] * 0.5j])
+    keys, first = np.unique(keys, return_index=True)
+    amps = amps[first]
+    amps /= np.linalg.norm(amps)
+    if prec == "c64":
+        amps = amps.astype(np.complex64).astype(np.complex128)
+    U = C.haar_unitary(rng, 32)
+    p = 0.0 if K else 0.95
+    say(f"[m5] {prec} N={len(keys)} K={K} p={p}")
+    kg, ag, sg = gpu_step(S, keys, amps, n, qubits, U, K, p, prec=prec, cap=len(keys) << 5)
+    ko, ao, info = oracle_step(keys, amps, qubits, U, K, p)
+    if prec == "c128":
+        assert_same_fp64(kg, ag, ko, ao)
+    else:
+        common, ig, io = np.intersect1d(kg, ko, assume_unique=True, return_indices=True)
+        assert len(common) >= 0.99 * len(ko)
+        assert np.abs(ag[ig] - ao[io]).max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("cap_factor", [1, 4])
 def test_four_qubit_gate_tiled_and_untiled(S, prec, cap_factor):
     # a state filling its capacity takes the untiled passes for a 4-qubit
