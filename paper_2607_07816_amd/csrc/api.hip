@@ -721,9 +721,9 @@ sts_status sts_truncate(sts_ctx *c)
     // last-workgroup counter
     const int sg = (int)std::min<u64>(std::max<u64>(ceil_div(std::min(cb, c->scap), 256), 1), STS_SIDE_GROUPS);
     STS_LAUNCH(c, STS_K_SIDE_HIST, launch_side_hist(b, c->h2, sg, c->stream));
-    // the extraction keeps no per-workgroup state: one workgroup per tile
-    // slab keeps every slab's loads in flight at once
-    STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, tiled ? std::max(sg, tt) : sg, c->stream));
+    // the extraction keeps no per-workgroup state: one wave per tile keeps
+    // every tile's loads in flight at once
+    STS_LAUNCH(c, STS_K_SIDE_EXTRACT, launch_side_extract(b, tiled ? std::max(sg, (tt + 3) / 4) : sg, c->stream));
     STS_LAUNCH(c, STS_K_FINAL, launch_final(b, c->stream));
     if (out_risk) {
         // only p-mass limits this cut: learn its size before writing

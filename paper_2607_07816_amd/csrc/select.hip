@@ -300,9 +300,13 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     // sums of those inside it
     if (e_w >= 0) {
         u64 v[6] = {0, 0, 0, 0, 0, 0};
-        for (int i = t; i < groups; i += 256) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f) v[f] += b.wpart[f * STS_MAX_GROUPS + i];
+        for (int r = 0; r < STS_MAX_GROUPS / 256; ++r) { // every load issued before any is used
+            const int i = t + 256 * r;
+            if (i < groups) {
+#pragma unroll
+                for (int f = 0; f < 6; ++f) v[f] += b.wpart[f * STS_MAX_GROUPS + i];
+            }
         }
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
@@ -756,19 +760,26 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
     const u64 region_base = (u64)region * region_len;
     u32 *cnt = &b.sub_cnt[region * 32];
     const u64 lt = sts_lanemask_lt();
-    for (u64 t = blockIdx.x; t < sc.nchunks; t += gridDim.x) {
+    // tiles (a few hundred window entries each): one wave per tile, so that
+    // every tile's wave is resident at once; dense runs: a workgroup per run
+    const bool per_wave = !sc.dense;
+    const u32 wv = threadIdx.x >> 6;
+    const u64 t0 = per_wave ? (u64)blockIdx.x * 4 + wv : (u64)blockIdx.x;
+    const u64 tstep = per_wave ? (u64)gridDim.x * 4 : (u64)gridDim.x;
+    const u32 nth = per_wave ? 64u : 256u, me = per_wave ? (u32)sts_lane() : (u32)threadIdx.x;
+    for (u64 t = t0; t < sc.nchunks; t += tstep) {
         const TileSlabs ch = chunk_of(sc, t);
         const u32 count = ch.n;
-        for (u32 i0 = 0; i0 < count; i0 += UN * 256) {
+        for (u32 i0 = 0; i0 < count; i0 += UN * nth) {
             u64 w[UN];
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
-                const u32 j = i0 + (u32)r * 256 + threadIdx.x;
+                const u32 j = i0 + (u32)r * nth + me;
                 w[r] = j < count ? b.side_w[slab_at(ch, j)] : ~0ull;
             }
 #pragma unroll
             for (int r = 0; r < UN; ++r) {
-                const u32 j = i0 + (u32)r * 256 + threadIdx.x;
+                const u32 j = i0 + (u32)r * nth + me;
                 const u64 i = j < count ? slab_at(ch, j) : 0ull;
                 bool take = false;
                 u64 k = 0;
@@ -804,6 +815,7 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
 // final levels and the exact cut, one workgroup of 1024 threads
 // ---------------------------------------------------------------------------
 constexpr int FT = 1024;
+constexpr int FB = 8; // subset entries a thread of the final workgroup loads at a time
 
 __global__ void __launch_bounds__(FT) k_final(PassBufs b)
 {
@@ -846,17 +858,41 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     // physical index of visited entry f (false: an empty slot of the side buffer)
     auto entry = [&](u64 f, u64 &i) -> bool {
         if (small) {
-            int lo = 0, hi = STS_SUB_REGIONS; // region r with pre[r] <= f < pre[r + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_regpre[mid] <= f) lo = mid;
-                else hi = mid;
-            }
+            int lo = 0; // the last region r with pre[r] <= f (then f < pre[r + 1])
+#pragma unroll
+            for (int step = STS_SUB_REGIONS / 2; step > 0; step >>= 1)
+                if (s_regpre[lo + step] <= f) lo += step;
             i = (u64)lo * region_len + (f - s_regpre[lo]);
             return true;
         }
         i = f;
         return side_valid(view, f);
+    };
+    // body(V) for every visited entry whose V lies under the prefix: FB
+    // entries per thread at a time, their loads in flight together (a loop
+    // of one entry at a time waits on a load per entry)
+    auto each_in_subset = [&](int vshift, u128 vpre, auto body) {
+        for (u64 f0 = t; f0 < n; f0 += (u64)FT * FB) {
+            u64 w[FB], k[FB], at[FB];
+            bool ok[FB];
+#pragma unroll
+            for (int r = 0; r < FB; ++r) {
+                const u64 f = f0 + (u64)FT * r;
+                u64 i = 0;
+                ok[r] = f < n && entry(f, i);
+                at[r] = ok[r] ? i : 0ull; // entry 0 exists: a harmless load
+            }
+#pragma unroll
+            for (int r = 0; r < FB; ++r) {
+                w[r] = src_w[at[r]];
+                k[r] = src_k[at[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < FB; ++r) {
+                const u128 v = rank_key(w[r], k[r]);
+                if (ok[r] && (v >> vshift) == vpre) body(v);
+            }
+        }
     };
     const u64 K = ctl->K;
     const u128 R = make128(ctl->R_lo, ctl->R_hi);
@@ -872,17 +908,13 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         const u128 vpre = s_sub.vpre;
         for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
         __syncthreads();
-        for (u64 f = t; f < n; f += FT) {
-            u64 i;
-            if (!entry(f, i)) continue;
-            const u128 v = rank_key(src_w[i], src_k[i]);
-            if ((v >> vshift) != vpre) continue;
+        each_in_subset(vshift, vpre, [&](const u128 v) {
             const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
             const u64 mant = mant_of_v(v, e);
             atomicAdd((unsigned long long *)&h_cnt[d], 1ull);
             atomicAdd((unsigned long long *)&h_hi[d], mant >> 26);
             atomicAdd((unsigned long long *)&h_lo[d], mant & ((1ull << 26) - 1));
-        }
+        });
         __syncthreads();
         if (!pick_digit<FT>(h_cnt, h_hi, h_lo, false, K, R, dw, &s_sub, s_m, s_c, &s_hit)) {
             if (t == 0) atomicOr(&ctl->flags, STS_F_UNRESOLVED);
@@ -895,14 +927,10 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     const u128 vpre = s_sub.vpre;
     if (t == 0) s_n = 0;
     __syncthreads();
-    for (u64 f = t; f < n; f += FT) {
-        u64 i;
-        if (!entry(f, i)) continue;
-        const u128 v = rank_key(src_w[i], src_k[i]);
-        if ((v >> vshift) != vpre) continue;
+    each_in_subset(vshift, vpre, [&](const u128 v) {
         const u32 slot = atomicAdd(&s_n, 1u);
         if (slot < STS_SMALL) sv[slot] = v;
-    }
+    });
     __syncthreads();
     const u32 m = s_n;
     if (m == 0 || m > STS_SMALL) {
@@ -1000,45 +1028,44 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_tile_kept(PassBufs b)
 {
+    // one wave per tile: a tile's window entries (a few hundred) take one
+    // round of loads, and every tile's wave is resident at once
     constexpr int UN = 4;
-    __shared__ u32 s_scratch[4];
     DevCtl *ctl = b.ctl;
-    const u64 tile = blockIdx.x; // below the tile arrays' length (the launch's bound)
+    const u64 tile = (u64)blockIdx.x * 4 + (threadIdx.x >> 6); // below the tile arrays' length
     // every control load issued before any is used
     const u64 n = *b.n_in;
     const u64 thr_w = ctl->thr_wbits, thr_k = ctl->thr_key;
     const int shift = ctl->side_slab_shift, spl = ctl->side_spt_log2;
     const u64 ntiles = (n + 2047) / 2048;
-    if (tile >= ntiles) return;
+    if (tile >= ntiles) return; // the whole wave
     // the tile's window entries (one slab, or one per wave of the histogram
     // pass), and its candidates certain before the cut
     const TileSlabs sd = tile_slabs(b.t_side, tile, spl, shift, false, b.side_cap);
     u64 na = 0;
     for (int w = 0; w < (1 << spl); ++w) na += b.t_above[(tile << spl) + (u64)w];
     const u32 ns = sd.n;
+    const u32 lane = (u32)sts_lane();
     u32 c = 0;
-    for (u32 i0 = 0; i0 < ns; i0 += UN * 256) {
+    for (u32 i0 = 0; i0 < ns; i0 += UN * 64) {
         u64 w[UN], k[UN];
 #pragma unroll
         for (int r = 0; r < UN; ++r) {
-            const u32 j = i0 + (u32)r * 256 + threadIdx.x;
-            if (j < ns) {
-                const u64 i = slab_at(sd, j);
-                w[r] = b.side_w[i];
-                k[r] = b.side_key[i];
-            }
+            const u32 j = i0 + (u32)r * 64 + lane;
+            const u64 i = j < ns ? slab_at(sd, j) : slab_at(sd, 0);
+            w[r] = b.side_w[i];
+            k[r] = b.side_key[i];
         }
 #pragma unroll
         for (int r = 0; r < UN; ++r) {
-            const u32 j = i0 + (u32)r * 256 + threadIdx.x;
-            if (j >= ns) continue;
+            const u32 j = i0 + (u32)r * 64 + lane;
             // ranked at or above the threshold term; the key decides only a tie
-            c += (w[r] > thr_w || (w[r] == thr_w && k[r] <= thr_k)) ? 1u : 0u;
+            c += (j < ns && (w[r] > thr_w || (w[r] == thr_w && k[r] <= thr_k))) ? 1u : 0u;
         }
     }
-    u32 tot;
-    (void)block_excl_scan<u32, 256>(c, s_scratch, &tot);
-    if (threadIdx.x == 0) b.t_off[tile] = na + tot;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane == 0) b.t_off[tile] = na + c;
 }
 
 __global__ void __launch_bounds__(1024) k_tile_scan(PassBufs b)
@@ -1168,7 +1195,7 @@ hipError_t launch_side_extract(const PassBufs &b, int grid, hipStream_t s)
 
 hipError_t launch_tile_kept(const PassBufs &b, int tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tile_kept, dim3(tiles), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_tile_kept, dim3((tiles + 3) / 4), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
