@@ -38,7 +38,7 @@ u64 align_up(u64 x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 struct Layout {
-    u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, side_amp, sub_key, sub_w, h1, h2, h2w, best, rcount, rprefix, rtotal, look_comp,
+    u64 ctl, ctl_save, keys[3], amps[3], side_key, side_w, side_amp, sub_key, sub_w, h1, h2, h2w, h3, best, rcount, rprefix, rtotal, look_comp,
         t_above, t_side, t_off, tctr, dU, sub_cnt, wpart, sbins, gate, total;
 };
 
@@ -73,6 +73,7 @@ Layout make_layout(u64 cap, int prec)
     L.h1 = take(3 * STS_NBIN * 8);
     L.h2 = take(3 * STS_NBIN * 8);
     L.h2w = take(3 * STS_NBIN * 8);
+    L.h3 = take(3 * STS_NBIN * 8);
     L.best = take(2 * STS_MAX_GROUPS * 8);
     L.rcount = take(2048 * tiles * 4); // per digit (up to 11-bit digits) and tile
     L.rprefix = take(2048 * tiles * 8);
@@ -139,7 +140,7 @@ struct sts_ctx {
     u64 n_bound = 1;        // upper bound on the terms in buffer cur
     DevCtl *ctl = nullptr;
     DevCtl *ctl_save = nullptr; // the control block as it was before a step that may be refused
-    u64 *h1 = nullptr, *h2 = nullptr, *h2w = nullptr, *best = nullptr;
+    u64 *h1 = nullptr, *h2 = nullptr, *h2w = nullptr, *h3 = nullptr, *best = nullptr;
     u64 *side_key = nullptr, *side_w = nullptr, *sub_key = nullptr, *sub_w = nullptr;
     void *side_amp = nullptr;
     u32 *rcount = nullptr;                          // per-tile digit counts of a scatter pass
@@ -257,6 +258,7 @@ PassBufs pass_bufs(sts_ctx *c, int in, int out)
     b.ctl = c->ctl;
     b.h1 = c->h1;
     b.h2w = c->h2w;
+    b.h3 = c->h3;
     b.best = c->best;
     b.side_key = c->side_key;
     b.side_w = c->side_w;
@@ -319,6 +321,7 @@ void bind_layout(sts_ctx *c, const Layout &L)
     c->h1 = (u64 *)(c->mem + L.h1);
     c->h2 = (u64 *)(c->mem + L.h2);
     c->h2w = (u64 *)(c->mem + L.h2w);
+    c->h3 = (u64 *)(c->mem + L.h3);
     c->best = (u64 *)(c->mem + L.best);
     c->rcount = (u32 *)(c->mem + L.rcount);
     c->rprefix = (u64 *)(c->mem + L.rprefix);

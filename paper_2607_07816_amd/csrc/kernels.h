@@ -36,6 +36,7 @@ struct PassBufs {
     // level-1 histogram (per exponent field) and per-workgroup best term
     u64 *h1;              // [3][STS_NBIN]: count, mantissa>>26, mantissa & (2^26-1)
     u64 *h2w;             // the same for level 2 of a sampled window (histogram pass)
+    u64 *h3;              // the same for the next level of the level-2 subset (the subset copy)
     u64 *best;            // [2][max groups]: (wbits | 2^63), key
     // compaction targets
     u64 *side_key;        // side buffer: candidates of the exponent holding the cut

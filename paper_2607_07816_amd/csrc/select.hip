@@ -164,6 +164,37 @@ __device__ inline void sub_store(const Sub &s, DevCtl *ctl)
 // 2048 bins held in (cnt[], hi[], lo[]) - global (agent loads) or LDS - by NT
 // threads, and narrow *sub to it. K, R: the rule (R all ones = no p-mass).
 // Returns false if no digit qualifies.
+// inclusive scan of (count, mass) pairs over a workgroup of NT threads, in
+// place: wave scans, then the wave totals through LDS (one barrier; sc, sm
+// hold NT / 64 entries and are not read again before the caller's next
+// barrier)
+template <int NT>
+__device__ __forceinline__ void block_scan_cm(u64 &c, u128 &m, u64 *sc, u128 *sm)
+{
+    const int lane = sts_lane(), w = (int)threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const u64 oc = __shfl_up(c, d, 64);
+        const u64 ol = __shfl_up((u64)m, d, 64), oh = __shfl_up((u64)(m >> 64), d, 64);
+        if (lane >= d) {
+            c += oc;
+            m += make128(ol, oh);
+        }
+    }
+    if (lane == 63) {
+        sc[w] = c;
+        sm[w] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        if (i < w) {
+            c += sc[i];
+            m += sm[i];
+        }
+    }
+}
+
 template <int NT>
 __device__ bool pick_digit(const u64 *cntp, const u64 *hip_, const u64 *lop, bool agent, u64 K, u128 R, int dw,
                            Sub *sub, u128 *s_m, u64 *s_c, u32 *s_hit)
@@ -189,26 +220,8 @@ __device__ bool pick_digit(const u64 *cntp, const u64 *hip_, const u64 *lop, boo
     }
     const u64 own_c = cc;
     const u128 own_m = mm;
-    s_c[t] = cc;
-    s_m[t] = mm;
     if (t == 0) *s_hit = 0xffffffffu;
-    __syncthreads();
-    for (int d = 1; d < NT; d <<= 1) {
-        u64 oc = 0;
-        u128 om = 0;
-        if (t >= d) {
-            oc = s_c[t - d];
-            om = s_m[t - d];
-        }
-        __syncthreads();
-        if (t >= d) {
-            cc += oc;
-            mm += om;
-            s_c[t] = cc;
-            s_m[t] = mm;
-        }
-        __syncthreads();
-    }
+    block_scan_cm<NT>(cc, mm, s_c, s_m);
     // exclusive prefix of this thread's bins, from the subset's start
     u64 cnt = sub->cnt_before + (cc - own_c);
     u128 m = sub->mb + (mm - own_m);
@@ -751,8 +764,13 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
     const SideChunks sc = side_chunks(b, ctl);
     const int vshift = ctl->vshift;
     const u128 vpre = make128(ctl->vpre_lo, ctl->vpre_hi);
+    const int e = ctl->e_star;
     if (keep_all || (flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW))) return;
     if (sub_count > b.sub_cap) return; // the final kernel reads the side buffer itself
+    // the subset's histogram for the next level (the digit below vshift),
+    // with exact mantissa sums, as the final workgroup's first level would
+    // bin it: that workgroup then starts from the pick
+    const int dw = vshift < 11 ? vshift : 11;
     // each wave fills one of STS_SUB_REGIONS regions, whose counters sit on
     // separate cache lines (one shared counter would serialise every wave)
     const u32 region = (blockIdx.x * 4u + (threadIdx.x >> 6)) % STS_SUB_REGIONS;
@@ -805,6 +823,14 @@ __global__ void __launch_bounds__(256) k_side_extract(PassBufs b)
                 if (take && pos < region_len) {
                     b.sub_key[region_base + pos] = k;
                     b.sub_w[region_base + pos] = w[r];
+                }
+                if (take && dw > 0) {
+                    const u128 v = rank_key(w[r], k);
+                    const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
+                    const u64 mant = mant_of_v(v, e);
+                    atomicAdd(&b.h3[d], 1ull);
+                    atomicAdd(&b.h3[STS_NBIN + d], mant >> 26);
+                    atomicAdd(&b.h3[2 * STS_NBIN + d], mant & ((1ull << 26) - 1));
                 }
             }
         }
@@ -896,6 +922,10 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     };
     const u64 K = ctl->K;
     const u128 R = make128(ctl->R_lo, ctl->R_hi);
+    // the subset copy binned the first of the levels below (the condition
+    // under which it copies the subset); the bins are cleared here for the
+    // next step, whether or not a level is needed
+    bool from_h3 = ctl->sub_count <= b.sub_cap;
     if (t == 0) sub_load(s_sub, ctl);
     __syncthreads();
 
@@ -906,21 +936,32 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         const int vshift = s_sub.vshift;
         const int dw = vshift < 11 ? vshift : 11;
         const u128 vpre = s_sub.vpre;
-        for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
-        __syncthreads();
-        each_in_subset(vshift, vpre, [&](const u128 v) {
-            const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
-            const u64 mant = mant_of_v(v, e);
-            atomicAdd((unsigned long long *)&h_cnt[d], 1ull);
-            atomicAdd((unsigned long long *)&h_hi[d], mant >> 26);
-            atomicAdd((unsigned long long *)&h_lo[d], mant & ((1ull << 26) - 1));
-        });
-        __syncthreads();
-        if (!pick_digit<FT>(h_cnt, h_hi, h_lo, false, K, R, dw, &s_sub, s_m, s_c, &s_hit)) {
+        bool ok;
+        if (from_h3) {
+            ok = pick_digit<FT>(b.h3, b.h3 + STS_NBIN, b.h3 + 2 * STS_NBIN, true, K, R, dw, &s_sub, s_m, s_c,
+                                &s_hit);
+            for (int i = t; i < 3 * STS_NBIN; i += FT) st_agent(&b.h3[i], 0ull);
+            from_h3 = false;
+        } else {
+            for (int i = t; i < 3 * STS_NBIN; i += FT) h_cnt[i] = 0;
+            __syncthreads();
+            each_in_subset(vshift, vpre, [&](const u128 v) {
+                const u32 d = (u32)((v >> (vshift - dw)) & (u128)((1u << dw) - 1));
+                const u64 mant = mant_of_v(v, e);
+                atomicAdd((unsigned long long *)&h_cnt[d], 1ull);
+                atomicAdd((unsigned long long *)&h_hi[d], mant >> 26);
+                atomicAdd((unsigned long long *)&h_lo[d], mant & ((1ull << 26) - 1));
+            });
+            __syncthreads();
+            ok = pick_digit<FT>(h_cnt, h_hi, h_lo, false, K, R, dw, &s_sub, s_m, s_c, &s_hit);
+        }
+        if (!ok) {
             if (t == 0) atomicOr(&ctl->flags, STS_F_UNRESOLVED);
             return;
         }
     }
+    if (from_h3) // binned, but the subset was small enough already
+        for (int i = t; i < 3 * STS_NBIN; i += FT) st_agent(&b.h3[i], 0ull);
 
     // gather the subset and sort it by V
     const int vshift = s_sub.vshift;
@@ -968,20 +1009,10 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         if (r < m) acc += (u128)mant_of_v(sv[r], e);
         loc[k] = acc;
     }
-    s_m[t] = acc;
     if (t == 0) s_hit = 0xffffffffu;
-    __syncthreads();
+    u64 none = 0;
     u128 inc = acc;
-    for (int d = 1; d < FT; d <<= 1) {
-        u128 o = 0;
-        if (t >= d) o = s_m[t - d];
-        __syncthreads();
-        if (t >= d) {
-            inc += o;
-            s_m[t] = inc;
-        }
-        __syncthreads();
-    }
+    block_scan_cm<FT>(none, inc, s_c, s_m);
     const u128 excl = inc - acc;
     const u64 cb = s_sub.cnt_before;
     const u128 mb = s_sub.mb;
