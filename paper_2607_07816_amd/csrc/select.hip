@@ -281,6 +281,8 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     __shared__ Sub s_sub;   // level 2 of a sampled window that holds the cut
     __shared__ u32 s_fine, s_hit2;
     __shared__ u64 s_sub_R_lo, s_sub_R_hi;
+    __shared__ u64 s_chunk[4][64]; // exact mass of each quarter of the bin list (a limb per lane)
+    __shared__ u64 s_chunk_c[4];   // and its count
     const int t = threadIdx.x;
     DevCtl *ctl = b.ctl;
     u64 *h1 = b.h1;
@@ -311,8 +313,10 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     // the window sums of the histogram workgroups: count of candidates above
     // the window and mantissa sums of those in its exponent, then count and
     // sums of those inside it
-    if (e_w >= 0) {
-        u64 v[6] = {0, 0, 0, 0, 0, 0};
+    // (loaded whenever the pass predicted, before the control block says
+    // whether a window was copied)
+    u64 v[6] = {0, 0, 0, 0, 0, 0};
+    if (predicted) {
 #pragma unroll
         for (int r = 0; r < STS_MAX_GROUPS / 256; ++r) { // every load issued before any is used
             const int i = t + 256 * r;
@@ -321,6 +325,8 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
                 for (int f = 0; f < 6; ++f) v[f] += b.wpart[f * STS_MAX_GROUPS + i];
             }
         }
+    }
+    if (e_w >= 0) {
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
 #pragma unroll
@@ -376,12 +382,29 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
     }
     __syncthreads();
 
-    if (t < 64) { // one wave: exact sums over the listed bins
+    // exact sums of the listed bins in four chunks, one wave each (a chain of
+    // exact additions per bin, a quarter as long as over all bins)
+    const u32 chunk = (nbins + 3) / 4;
+    {
+        const int q = t >> 6;
+        const u32 j0 = (u32)q * chunk, j1 = j0 + chunk < nbins ? j0 + chunk : nbins;
+        u64 C = 0, nc = 0;
+        for (u32 j = j0; j < j1; ++j) {
+            C = wl_add(C, wl_piece(s_lo[j], s_hi[j], unit_bit((int)s_e[j])));
+            nc += s_c[j];
+        }
+        s_chunk[q][t & 63] = C;
+        if ((t & 63) == 0) s_chunk_c[q] = nc;
+    }
+    __syncthreads();
+
+    if (t < 64) { // one wave: the total, the target and the cut's bin
         const int lane = t;
         u64 W = 0, total_c = 0;
-        for (u32 j = 0; j < nbins; ++j) {
-            W = wl_add(W, wl_piece(s_lo[j], s_hi[j], unit_bit((int)s_e[j])));
-            total_c += s_c[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            W = wl_add(W, s_chunk[q][lane]);
+            total_c += s_chunk_c[q];
         }
         const double Wd = wl_to_double(W);
         if (peak_only) {
@@ -419,19 +442,31 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
                 ctl->tot_updates += *b.n_in;
                 ctl->tot_cand += total_c;
             }
-            // the first bin in rank order where the rule is met
+            // the first bin in rank order where the rule is met: the first
+            // chunk through which it is met (the rule only grows along the
+            // ranking), then that chunk's bins
             u64 S = 0, cnt = 0;
             u32 hit = 0xffffffffu;
-            for (u32 j = 0; j < nbins; ++j) {
-                const u64 inc = wl_add(S, wl_piece(s_lo[j], s_hi[j], unit_bit((int)s_e[j])));
-                const bool hk = K > 0 && cnt + s_c[j] >= K;
-                const bool hp = p_on && wl_cmp(inc, T) >= 0;
-                if (hk || hp) {
-                    hit = j;
+            for (int q = 0; q < 4; ++q) {
+                const u64 inc_q = wl_add(S, s_chunk[q][lane]);
+                const bool met_q = (K > 0 && cnt + s_chunk_c[q] >= K) || (p_on && wl_cmp(inc_q, T) >= 0);
+                if (met_q) {
+                    const u32 j0 = (u32)q * chunk, j1 = j0 + chunk < nbins ? j0 + chunk : nbins;
+                    for (u32 j = j0; j < j1; ++j) {
+                        const u64 inc = wl_add(S, wl_piece(s_lo[j], s_hi[j], unit_bit((int)s_e[j])));
+                        const bool hk = K > 0 && cnt + s_c[j] >= K;
+                        const bool hp = p_on && wl_cmp(inc, T) >= 0;
+                        if (hk || hp) {
+                            hit = j;
+                            break;
+                        }
+                        S = inc;
+                        cnt += s_c[j];
+                    }
                     break;
                 }
-                S = inc;
-                cnt += s_c[j];
+                S = inc_q;
+                cnt += s_chunk_c[q];
             }
             if (hit == 0xffffffffu) {
                 if (lane == 0) {
