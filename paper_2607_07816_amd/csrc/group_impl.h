@@ -1287,7 +1287,7 @@ template <typename AT>
 __device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int spl, int shift, u64 out0, u64 thr_w,
                                               u64 thr_k, bool rescale, double scale, u32 *s_scan)
 {
-    constexpr int UN = 4;
+    constexpr int UN = 8; // a tile's survivors above the window (about 2048) in one round of loads
     const TileSlabs ab = tile_slabs(b.t_above, tile, spl, shift, true, b.side_cap);
     const TileSlabs sd = tile_slabs(b.t_side, tile, spl, shift, false, b.side_cap);
     const u32 na = ab.n, ns = sd.n;
@@ -1300,9 +1300,11 @@ __device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int s
         for (int r = 0; r < UN; ++r) {
             const u32 j = j0 + (u32)r * STS_WG + threadIdx.x;
             if (j < na) {
+                // the slabs are read once: non-temporal loads
                 const u64 i = slab_at(ab, j);
-                kk[r] = b.side_key[i];
-                aa[r] = sa[i];
+                kk[r] = __builtin_nontemporal_load(&b.side_key[i]);
+                aa[r].x = __builtin_nontemporal_load(&sa[i].x);
+                aa[r].y = __builtin_nontemporal_load(&sa[i].y);
             }
         }
 #pragma unroll
