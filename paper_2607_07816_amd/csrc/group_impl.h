@@ -1311,8 +1311,12 @@ __device__ __forceinline__ void tile_copy_out(const PassBufs &b, u64 tile, int s
         for (int r = 0; r < UN; ++r) {
             const u32 j = j0 + (u32)r * STS_WG + threadIdx.x;
             if (j < na && out0 + j < b.out_cap) {
+                // the amplitudes bypass the caches, which then hold the keys
+                // for the next step's first counting pass
                 b.out_keys[out0 + j] = kk[r];
-                oa[out0 + j] = out_amp(aa[r], rescale, scale);
+                const AT o = out_amp(aa[r], rescale, scale);
+                __builtin_nontemporal_store(o.x, &oa[out0 + j].x);
+                __builtin_nontemporal_store(o.y, &oa[out0 + j].y);
             }
         }
     }
