@@ -560,11 +560,11 @@ __global__ void __launch_bounds__(256) k_pick1(PassBufs b, int groups, int peak_
         u64 *s_c2 = s_hi;
         const bool ok = pick_digit<256>(b.h2w, b.h2w + STS_NBIN, b.h2w + 2 * STS_NBIN, true, ctl->K, R, 11, &s_sub,
                                         s_m, s_c2, &s_hit2);
+        if (ok && t <= STS_SUB_REGIONS) st_agent(&b.sub_cnt[t * 32], 0u);
         if (t == 0) {
             if (ok) {
                 sub_store(s_sub, ctl);
                 ctl->level = 2;
-                for (int i = 0; i <= STS_SUB_REGIONS; ++i) st_agent(&b.sub_cnt[i * 32], 0u);
                 ctl->l2_done = 1;
             } else {
                 atomicOr(&ctl->flags, STS_F_UNRESOLVED);
@@ -768,10 +768,10 @@ __global__ void __launch_bounds__(256) k_side_hist(PassBufs b, u64 *h2)
         __syncthreads();
         const u128 R = make128(ctl->R_lo, ctl->R_hi);
         if (pick_digit<256>(hs, hs + STS_NBIN, hs + 2 * STS_NBIN, true, ctl->K, R, 11, &s_sub, s_m, s_c, &s_hit)) {
+            if (threadIdx.x <= STS_SUB_REGIONS) st_agent(&b.sub_cnt[threadIdx.x * 32], 0u);
             if (threadIdx.x == 0) {
                 sub_store(s_sub, ctl);
                 ctl->level = 2;
-                for (int i = 0; i <= STS_SUB_REGIONS; ++i) st_agent(&b.sub_cnt[i * 32], 0u);
             }
         } else if (threadIdx.x == 0) {
             atomicOr(&ctl->flags, STS_F_UNRESOLVED);
@@ -897,6 +897,17 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     if (ctl->flags & (STS_F_UNRESOLVED | STS_F_SIDE_OVERFLOW)) return;
     const int t = threadIdx.x;
     const int e = ctl->e_star;
+    // the subset and what the cut's thread needs at the end, loaded now
+    // (visible after the barrier below)
+    __shared__ u64 s_Sx[STS_NL], s_ncand;
+    __shared__ double s_W, s_l10;
+    if (t == 0) {
+        sub_load(s_sub, ctl);
+        s_ncand = ctl->n_cand;
+        s_W = ctl->W;
+        s_l10 = ctl->log10_cum;
+    }
+    if (t < STS_NL) s_Sx[t] = ctl->S_excl.l[t];
     // the subset regions when they hold the whole subset, else the side buffer
     // (entries of region r at r * region_len + [0, count_r); visited through
     // an exclusive prefix of the counts, so only filled slots are read)
@@ -961,8 +972,6 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
     // under which it copies the subset); the bins are cleared here for the
     // next step, whether or not a level is needed
     bool from_h3 = ctl->sub_count <= b.sub_cap;
-    if (t == 0) sub_load(s_sub, ctl);
-    __syncthreads();
 
     // further levels until the subset is small (a level is a pass over the
     // subset and a block scan; the bitonic sort below costs a barrier per
@@ -1073,19 +1082,22 @@ __global__ void __launch_bounds__(FT) k_final(PassBufs b)
         const u128 v = sv[first];
         const u64 frac = ((1ull << 52) - 1) - (u64)(v >> 64);
         const u128 mk = mb + excl + loc[k];
-        Big S = ctl->S_excl;
+        Big S;
+#pragma unroll
+        for (int i = 0; i < STS_NL; ++i) S.l[i] = s_Sx[i];
         big_add_shifted(S, (u64)mk, (u64)(mk >> 64), unit_bit(e));
         const double Sd = big_to_double(S);
         const u64 L = cb + first + 1;
-        const int dropped = L < ctl->n_cand;
+        const int dropped = L < s_ncand;
         ctl->L = L;
         ctl->thr_wbits = ((u64)e << 52) | frac;
         ctl->thr_key = (u64)v;
         ctl->dropped = dropped;
         ctl->S = Sd;
         ctl->scale = dropped ? 1.0 / sqrt(Sd) : 1.0;
-        ctl->frac = Sd / ctl->W;
-        if (dropped) ctl->log10_cum += log10(ctl->frac);
+        const double frac_kept = Sd / s_W;
+        ctl->frac = frac_kept;
+        if (dropped) ctl->log10_cum = s_l10 + log10(frac_kept);
     }
 }
 
