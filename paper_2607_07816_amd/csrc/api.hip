@@ -712,8 +712,10 @@ sts_status sts_truncate(sts_ctx *c)
         if (!c->hctl->keep_all && c->hctl->sub_count > c->scap) return refuse_step(c);
     }
     if (tiled) {
+        // as many workgroups as the histogram pass keeps resident: one round
+        // of launches when the window held the cut and every one exits
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT,
-                   launch_group_extract_tiles(c->prec, c->gate, b, std::min(tt, 2048), c->stream));
+                   launch_group_extract_tiles(c->prec, c->gate, b, std::min(tt, G), c->stream));
     } else {
         b.epoch = next_epoch(c);
         STS_LAUNCH(c, STS_K_GROUP_EXTRACT,

@@ -10,8 +10,9 @@
 //   level 2  - within that exponent, the top 11 bits of the within-exponent
 //              rank key V = ((2^52 - 1 - fraction) << 64) | key, from the side
 //              buffer of that exponent's candidates,
-//   level 3+ - further 11-bit digits of V inside one workgroup, until at most
-//              512 terms remain; those are sorted in LDS.
+//   level 3+ - further 11-bit digits of V inside one workgroup (level 3 from
+//              a histogram built while the level-2 subset is copied out),
+//              until at most 512 terms remain; those are sorted in LDS.
 // Masses are exact: each bin carries the exact integer sum of its weights'
 // mantissas, levels >= 2 share one exponent, and level 1 prefixes are exact
 // integers on the 2^-1074 grid. Every decision therefore equals the one made
